@@ -1,0 +1,198 @@
+"""CPU oracle for the fewbody Hermite integrator -- TEST INFRASTRUCTURE ONLY.
+
+A ctypes wrapper around ``hermite_oracle.c`` (plain FP64 C, built with
+``-O2 -ffp-contract=off``).  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product library
+never does.  It shares no code with the HIP path: the only inputs both sides
+see come from the seeded generators.
+
+Every routine works on one system with bodies in rows (body 0 = star):
+``mass[n]``, ``pos[n, 3]``, ``vel[n, 3]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hermite_oracle.c")
+LIB = os.environ.get("FEWBODY_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
+
+ACTIVE, DONE, ENCOUNTER, EJECTED, NONFINITE, STALLED_DT, MAXSTEPS = range(7)
+STOP_ENCOUNTER, STOP_EJECT = 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain FP64, no contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                               "-Wall", "-fPIC", "-shared", "-o", tmp, SRC, "-lm", "-lpthread"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        d, i, l, p = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
+        L.ora_accjerk.argtypes = [i, p, p, p, p, p]
+        L.ora_predict.argtypes = [i, d, p, p, p, p, p, p]
+        L.ora_correct.argtypes = [i, d, p, p, p, p, p, p, p, p]
+        L.ora_integrate_fixed.argtypes = [i, p, p, p, p, p, d, l, i, i]
+        L.ora_integrate_fixed.restype = i
+        L.ora_energy.argtypes = [i, p, p, p, p, p]
+        L.ora_pair_timestep.argtypes = [i, p, p, p, d]
+        L.ora_pair_timestep.restype = d
+        L.ora_check_stop.argtypes = [i, p, p, p, i, d]
+        L.ora_check_stop.restype = i
+        L.ora_integrate_adaptive.argtypes = [i, p, p, p, p, p, p, d, d, i, d, l, p, p, i]
+        L.ora_integrate_adaptive.restype = i
+        L.ora_ensemble_fixed.argtypes = [i, p, p, p, p, p, p, d, l, i, i, i]
+        L.ora_ensemble_fixed.restype = i
+        L.ora_ensemble_energy.argtypes = [i, p, p, p, p, p, p]
+        L.ora_ensemble_energy.restype = i
+        _lib = L
+    return _lib
+
+
+def _f64(a, shape=None):
+    out = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        out = out.reshape(shape)
+    return out
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def accjerk(mass, pos, vel):
+    """Acceleration and jerk of every body (Eq. 1 and its time derivative)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)), _f64(vel, (n, 3))
+    a, j = np.zeros((n, 3)), np.zeros((n, 3))
+    lib().ora_accjerk(n, _p(m), _p(x), _p(v), _p(a), _p(j))
+    return a, j
+
+
+def predict(h, x0, v0, a0, j0):
+    n = np.asarray(x0).reshape(-1, 3).shape[0]
+    arrs = [_f64(z, (n, 3)) for z in (x0, v0, a0, j0)]
+    xp, vp = np.zeros((n, 3)), np.zeros((n, 3))
+    lib().ora_predict(n, float(h), *[_p(z) for z in arrs], _p(xp), _p(vp))
+    return xp, vp
+
+
+def correct(h, xp, vp, a0, j0, ak, jk):
+    n = np.asarray(xp).reshape(-1, 3).shape[0]
+    arrs = [_f64(z, (n, 3)) for z in (xp, vp, a0, j0, ak, jk)]
+    xc, vc = np.zeros((n, 3)), np.zeros((n, 3))
+    lib().ora_correct(n, float(h), *[_p(z) for z in arrs], _p(xc), _p(vc))
+    return xc, vc
+
+
+def integrate_fixed(mass, pos, vel, h, nsteps, n_corr=2, acc=None, jerk=None,
+                    converged=False):
+    """Fixed-step P(EC)^n_corr integration of one system.
+
+    If ``acc``/``jerk`` are None the set-up evaluation computes them.
+    Returns (pos, vel, acc0, jerk0) after ``nsteps`` steps."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)).copy(), _f64(vel, (n, 3)).copy()
+    flags = 0
+    if acc is None or jerk is None:
+        a, j = np.zeros((n, 3)), np.zeros((n, 3))
+        flags |= 1
+    else:
+        a, j = _f64(acc, (n, 3)).copy(), _f64(jerk, (n, 3)).copy()
+    if converged:
+        flags |= 2
+    rc = lib().ora_integrate_fixed(n, _p(m), _p(x), _p(v), _p(a), _p(j), float(h),
+                                   int(nsteps), int(n_corr), flags)
+    if rc != 0:
+        raise ValueError("oracle rejected arguments")
+    return x, v, a, j
+
+
+def energy(mass, pos, vel):
+    """(E, L[3]) of one system: Eq. 6 with pairs counted once, L = sum m x cross v."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)), _f64(vel, (n, 3))
+    e = np.zeros(1)
+    L = np.zeros(3)
+    lib().ora_energy(n, _p(m), _p(x), _p(v), _p(e), _p(L))
+    return float(e[0]), L
+
+
+def pair_timestep(mass, pos, vel, eta):
+    m = _f64(mass)
+    n = m.shape[0]
+    return lib().ora_pair_timestep(n, _p(m), _p(_f64(pos, (n, 3))), _p(_f64(vel, (n, 3))), float(eta))
+
+
+def check_stop(mass, pos, vel, stop_rules=3, r_eject=100.0):
+    m = _f64(mass)
+    n = m.shape[0]
+    return lib().ora_check_stop(n, _p(m), _p(_f64(pos, (n, 3))), _p(_f64(vel, (n, 3))),
+                                int(stop_rules), float(r_eject))
+
+
+def integrate_adaptive(mass, pos, vel, t_end, eta=0.01, stop_rules=3, r_eject=100.0,
+                       max_steps=10**9, t0=0.0):
+    """Adaptive integration of one system to t_end or a stop rule.
+
+    Returns dict(pos, vel, acc, jerk, t, dt_next, steps, status)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)).copy(), _f64(vel, (n, 3)).copy()
+    a, j = np.zeros((n, 3)), np.zeros((n, 3))
+    t = np.array([t0], dtype=np.float64)
+    dtn = np.zeros(1)
+    steps = np.zeros(1, dtype=np.int64)
+    st = lib().ora_integrate_adaptive(n, _p(m), _p(x), _p(v), _p(a), _p(j), _p(t), float(t_end),
+                                      float(eta), int(stop_rules), float(r_eject), int(max_steps),
+                                      _p(dtn), _p(steps), 1)
+    return {"pos": x, "vel": v, "acc": a, "jerk": j, "t": float(t[0]), "dt_next": float(dtn[0]),
+            "steps": int(steps[0]), "status": int(st)}
+
+
+def ensemble_fixed(n_body, mass, pos, vel, h, nsteps, n_corr=2, nthreads=1):
+    """Integrate a ragged ensemble (flat arrays) for nsteps fixed steps.
+
+    Returns (pos, vel, acc0, jerk0) as new flat arrays."""
+    nb = np.ascontiguousarray(n_body, dtype=np.int32)
+    m = _f64(mass)
+    N = m.shape[0]
+    x, v = _f64(pos, (N, 3)).copy(), _f64(vel, (N, 3)).copy()
+    a, j = np.zeros((N, 3)), np.zeros((N, 3))
+    rc = lib().ora_ensemble_fixed(int(nb.shape[0]), _p(nb), _p(m), _p(x), _p(v), _p(a), _p(j),
+                                  float(h), int(nsteps), int(n_corr), 1, int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected arguments")
+    return x, v, a, j
+
+
+def ensemble_energy(n_body, mass, pos, vel):
+    nb = np.ascontiguousarray(n_body, dtype=np.int32)
+    m = _f64(mass)
+    N = m.shape[0]
+    E = np.zeros(nb.shape[0])
+    L = np.zeros((nb.shape[0], 3))
+    rc = lib().ora_ensemble_energy(int(nb.shape[0]), _p(nb), _p(m), _p(_f64(pos, (N, 3))),
+                                   _p(_f64(vel, (N, 3))), _p(E), _p(L))
+    if rc != 0:
+        raise ValueError("oracle rejected arguments")
+    return E, L

@@ -1,0 +1,495 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a closed-form orbit, a
+polynomial identity of the Hermite scheme, a conservation law, a symmetry,
+or an exact rounding outcome.  A dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests import kepler
+
+pytestmark = []
+rng0 = np.random.default_rng(12345)
+
+
+# --------------------------------------------------------------------------
+# Predictor and corrector (Eq. 3, Eq. 4 as read: 3/20 coefficient, h^3 jerk
+# term, predicted state as base) -- polynomial exactness.
+# --------------------------------------------------------------------------
+def _poly_traj(rng, deg_acc):
+    """Random per-component polynomial acceleration a(t) of degree deg_acc,
+    with v(t), x(t) its exact integrals (numpy.polynomial, no Hermite code)."""
+    P = np.polynomial.Polynomial
+    comps = []
+    for _ in range(6):  # 2 bodies x 3 components
+        acc = P(rng.uniform(-1, 1, deg_acc + 1))
+        vel = acc.integ(k=[rng.uniform(-1, 1)])
+        pos = vel.integ(k=[rng.uniform(-1, 1)])
+        comps.append((pos, vel, acc, acc.deriv()))
+    def at(t, k):
+        return np.array([c[k](t) for c in comps]).reshape(2, 3)
+    return at
+
+
+def test_predictor_exact_for_cubic_trajectory(ora):
+    """Eq. 3 is the Taylor polynomial to the jerk: exact for cubic x(t)."""
+    rng = np.random.default_rng(1)
+    at = _poly_traj(rng, 1)      # a linear -> x cubic
+    for h in (0.3, -0.7, 1.9):
+        xp, vp = ora.predict(h, at(0, 0), at(0, 1), at(0, 2), at(0, 3))
+        np.testing.assert_allclose(xp, at(h, 0), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(vp, at(h, 1), rtol=0, atol=1e-14)
+
+
+def test_predictor_not_exact_for_quartic(ora):
+    rng = np.random.default_rng(2)
+    at = _poly_traj(rng, 2)      # a quadratic -> predictor misses the snap term
+    h = 0.5
+    xp, _ = ora.predict(h, at(0, 0), at(0, 1), at(0, 2), at(0, 3))
+    assert np.abs(xp - at(h, 0)).max() > 1e-6
+
+
+@pytest.mark.parametrize("h", [0.25, 0.8, -0.6])
+def test_corrector_exact_for_cubic_acceleration(ora, h):
+    """With a prescribed cubic a(t) (independent of x), the two-point Hermite
+    corrector reproduces v(h) and x(h) exactly (v: Hermite quadrature exact
+    for cubic integrands; x: exact for quintic v)."""
+    rng = np.random.default_rng(3)
+    at = _poly_traj(rng, 3)
+    x0, v0, a0, j0 = at(0, 0), at(0, 1), at(0, 2), at(0, 3)
+    xp, vp = ora.predict(h, x0, v0, a0, j0)
+    xc, vc = ora.correct(h, xp, vp, a0, j0, at(h, 2), at(h, 3))
+    np.testing.assert_allclose(vc, at(h, 1), rtol=0, atol=2e-14)
+    np.testing.assert_allclose(xc, at(h, 0), rtol=0, atol=2e-14)
+
+
+def test_corrector_error_order_for_quartic_acceleration(ora):
+    """Beyond cubic a(t) the corrector is no longer exact; its local error in
+    v must scale as h^5 (halving h divides it by 32)."""
+    rng = np.random.default_rng(4)
+    at = _poly_traj(rng, 4)
+    errs = []
+    for h in (0.2, 0.1, 0.05):
+        x0, v0, a0, j0 = at(0, 0), at(0, 1), at(0, 2), at(0, 3)
+        xp, vp = ora.predict(h, x0, v0, a0, j0)
+        _, vc = ora.correct(h, xp, vp, a0, j0, at(h, 2), at(h, 3))
+        errs.append(np.abs(vc - at(h, 1)).max())
+    assert errs[0] > 1e-10
+    assert 28 < errs[0] / errs[1] < 36 and 28 < errs[1] / errs[2] < 36
+
+
+# --------------------------------------------------------------------------
+# Whole integrator vs closed-form Kepler orbits
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("e", [0.0, 0.05, 0.3])
+def test_two_body_matches_kepler(ora, e):
+    m0, m1, a = 1.0, 1e-3, 1.0
+    mu = m0 + m1
+    P = 2 * math.pi * math.sqrt(a ** 3 / mu)
+    steps_per_orbit = 1000 if e < 0.1 else 4000
+    h = P / steps_per_orbit
+    x, v = kepler.two_body_state(m0, m1, a, e, 0.0)
+    m = np.array([m0, m1])
+    nsteps = 3 * steps_per_orbit + 17
+    xf, vf, _, _ = ora.integrate_fixed(m, x, v, h, nsteps)
+    xe, ve = kepler.two_body_state(m0, m1, a, e, nsteps * h)
+    err = max(np.abs(xf - xe).max(), np.abs(vf - ve).max())
+    assert err < 2e-9, err
+
+
+def test_two_body_fourth_order_convergence(ora):
+    """Halving h divides the global error at a fixed time by ~16."""
+    m0, m1, a, e = 1.0, 1e-3, 1.0, 0.05
+    mu = m0 + m1
+    T = 2 * math.pi * math.sqrt(a ** 3 / mu)
+    m = np.array([m0, m1])
+    x, v = kepler.two_body_state(m0, m1, a, e, 0.0)
+    xe, _ = kepler.two_body_state(m0, m1, a, e, T)
+    errs = []
+    for N in (250, 500, 1000):
+        xf, _, _, _ = ora.integrate_fixed(m, x, v, T / N, N)
+        errs.append(np.abs(xf - xe).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 14 < r1 < 18 and 14 < r2 < 18, (errs, r1, r2)
+
+
+@pytest.mark.parametrize("n", [3, 5, 9, 15, 16])
+def test_massless_planets_follow_kepler(ora, n):
+    """Massless planets feel only the star (mu = m0) and the star does not
+    move: every body has a closed-form orbit, for every body index."""
+    rng = np.random.default_rng(n)
+    m = np.zeros(n)
+    m[0] = 1.0
+    x = np.zeros((n, 3))
+    v = np.zeros((n, 3))
+    for i in range(1, n):
+        a = 1.0 + 0.3 * i
+        r = a * (1 + rng.uniform(-0.05, 0.05))
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        t = np.cross(d, rng.normal(size=3))
+        t /= np.linalg.norm(t)
+        x[i] = r * d
+        v[i] = math.sqrt(1.0 / r) * (1 + rng.uniform(-0.04, 0.04)) * t
+    h = 2 * math.pi / 2000
+    N = 2500
+    xf, vf, _, _ = ora.integrate_fixed(m, x, v, h, N)
+    assert np.all(xf[0] == 0.0) and np.all(vf[0] == 0.0)
+    for i in range(1, n):
+        xe, ve = kepler.propagate(x[i], v[i], 1.0, N * h)
+        assert np.abs(xf[i] - xe).max() < 5e-10, i
+        assert np.abs(vf[i] - ve).max() < 5e-10, i
+
+
+def _ring(K, M, m, R, tilt_seed=None):
+    """Star M at the centre of a regular K-gon of planets m at radius R: a
+    rigidly rotating solution with w^2 = (M + m S/4)/R^3, S = sum_k 1/sin(pi k/K)."""
+    S = sum(1.0 / math.sin(math.pi * k / K) for k in range(1, K))
+    w = math.sqrt((M + m * S / 4.0) / R ** 3)
+    th = 2 * math.pi * np.arange(K) / K
+    def state(t):
+        ang = th + w * t
+        x = np.zeros((K + 1, 3))
+        v = np.zeros((K + 1, 3))
+        x[1:, 0], x[1:, 1] = R * np.cos(ang), R * np.sin(ang)
+        v[1:, 0], v[1:, 1] = -w * R * np.sin(ang), w * R * np.cos(ang)
+        return x, v
+    Q = np.eye(3)
+    if tilt_seed is not None:
+        Q, _ = np.linalg.qr(np.random.default_rng(tilt_seed).normal(size=(3, 3)))
+    def rot_state(t):
+        x, v = state(t)
+        return x @ Q.T, v @ Q.T
+    mass = np.concatenate([[M], np.full(K, m)])
+    return mass, rot_state, 2 * math.pi / w
+
+
+@pytest.mark.parametrize("K,m", [(2, 1e-3), (4, 1e-2), (7, 3e-2), (14, 1e-2), (15, 1e-2)])
+def test_ring_central_configuration(ora, K, m):
+    """Planet-planet forces at full strength: the tilted ring rotates rigidly
+    (one period; heavy rings are unstable equilibria, so longer runs would
+    measure the growth of roundoff rather than the scheme)."""
+    mass, st, T = _ring(K, 1.0, m, 1.3, tilt_seed=K)
+    x0, v0 = st(0.0)
+    N = 1000
+    h = T / 1000
+    xf, vf, _, _ = ora.integrate_fixed(mass, x0, v0, h, N)
+    xe, ve = st(N * h)
+    assert np.abs(xf - xe).max() < 1e-10
+    assert np.abs(vf - ve).max() < 1e-10
+
+
+def test_ring_error_is_fourth_order(ora):
+    mass, st, T = _ring(9, 1.0, 2e-2, 1.1, tilt_seed=3)
+    x0, v0 = st(0.0)
+    errs = []
+    for N in (200, 400):
+        xf, _, _, _ = ora.integrate_fixed(mass, x0, v0, T / N, N)
+        errs.append(np.abs(xf - st(T)[0]).max())
+    assert 14 < errs[0] / errs[1] < 18, errs
+
+
+def test_lagrange_triangle_unequal_masses(ora):
+    """Three unequal masses on an equilateral triangle rotate rigidly about the
+    centre of mass with w^2 = (m1+m2+m3)/d^3 (Lagrange's solution)."""
+    m = np.array([1.0, 0.3, 0.05])
+    d = 1.7
+    P = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0], [d / 2, d * math.sqrt(3) / 2, 0.0]])
+    P -= (m[:, None] * P).sum(0) / m.sum()
+    w = math.sqrt(m.sum() / d ** 3)
+    def state(t):
+        c, s = math.cos(w * t), math.sin(w * t)
+        Rz = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+        x = P @ Rz.T
+        v = np.stack([-w * x[:, 1], w * x[:, 0], np.zeros(3)], axis=1)
+        return x, v
+    x0, v0 = state(0.0)
+    T = 2 * math.pi / w
+    N = 2000
+    xf, vf, _, _ = ora.integrate_fixed(m, x0, v0, T / 1000, N)
+    xe, ve = state(N * T / 1000)
+    assert np.abs(xf - xe).max() < 1e-9
+    assert np.abs(vf - ve).max() < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Force and jerk
+# --------------------------------------------------------------------------
+def test_acceleration_simple_cases(ora):
+    m = np.array([1.0, 2.0])
+    x = np.array([[0.0, 0.0, 0.0], [0.0, 2.0, 0.0]])
+    v = np.zeros((2, 3))
+    a, j = ora.accjerk(m, x, v)
+    np.testing.assert_array_equal(a, [[0, 0.5, 0], [0, -0.25, 0]])
+    np.testing.assert_array_equal(j, np.zeros((2, 3)))
+    # radial approach: r = (3,0,0), u = (-1,0,0): j on body 0 = m1 (u/r^3 - 3 (r.u) r/r^5) = m1 * (2/27, 0, 0)
+    m = np.array([1.0, 1.0])
+    x = np.array([[0.0, 0, 0], [3.0, 0, 0]])
+    v = np.array([[0.0, 0, 0], [-1.0, 0, 0]])
+    a, j = ora.accjerk(m, x, v)
+    np.testing.assert_allclose(j[0], [2.0 / 27, 0, 0], rtol=1e-15)
+    np.testing.assert_allclose(j[1], [-2.0 / 27, 0, 0], rtol=1e-15)
+    # tangential motion: u perpendicular to r: j = m u / r^3
+    v = np.array([[0.0, 0, 0], [0.0, 0.5, 0]])
+    _, j = ora.accjerk(m, x, v)
+    np.testing.assert_allclose(j[0], [0, 0.5 / 27, 0], rtol=1e-15)
+
+
+@pytest.mark.parametrize("n", [3, 6, 11])
+def test_acceleration_is_minus_gradient_of_potential(ora, n):
+    """a_i = -(1/m_i) dU/dx_i with U = -sum_{i<j} m_i m_j / r_ij taken from the
+    energy routine at zero velocity (central differences)."""
+    rng = np.random.default_rng(40 + n)
+    m = rng.uniform(0.2, 1.0, n)
+    x = rng.normal(size=(n, 3)) * 2
+    v = np.zeros((n, 3))
+    a, _ = ora.accjerk(m, x, v)
+    eps = 1e-5
+    for i in range(n):
+        for c in range(3):
+            xp = x.copy(); xp[i, c] += eps
+            xm = x.copy(); xm[i, c] -= eps
+            Up, _ = ora.energy(m, xp, v)
+            Um, _ = ora.energy(m, xm, v)
+            g = (Up - Um) / (2 * eps)
+            assert abs(-g / m[i] - a[i, c]) < 1e-8 * max(1.0, abs(a[i, c]))
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 15])
+def test_jerk_is_time_derivative_of_acceleration(ora, n):
+    """j = d a / dt along x + v t (central finite difference, error O(d^2))."""
+    rng = np.random.default_rng(n)
+    m = rng.uniform(0.1, 1.0, n)
+    x = rng.normal(size=(n, 3)) * 3
+    v = rng.normal(size=(n, 3))
+    _, j = ora.accjerk(m, x, v)
+    d = 1e-5
+    ap, _ = ora.accjerk(m, x + d * v, v)
+    am, _ = ora.accjerk(m, x - d * v, v)
+    fd = (ap - am) / (2 * d)
+    assert np.abs(fd - j).max() < 1e-7 * max(1.0, np.abs(j).max())
+
+
+def test_third_law_total_force_and_momentum(ora):
+    rng = np.random.default_rng(7)
+    n = 12
+    m = rng.uniform(1e-4, 1.0, n)
+    x = rng.normal(size=(n, 3)) * 2
+    v = rng.normal(size=(n, 3))
+    a, j = ora.accjerk(m, x, v)
+    assert np.abs((m[:, None] * a).sum(0)).max() < 1e-13 * np.abs(m[:, None] * a).max()
+    assert np.abs((m[:, None] * j).sum(0)).max() < 1e-13 * np.abs(m[:, None] * j).max()
+
+
+def test_star_contribution_is_added_last(ora):
+    """Exact rounding pin of the summation order (Section 4.2: the star's
+    contribution is accumulated after the planets').  Planet 1 feels exactly
+    0.375 ulp(1) from each of planets 2 and 3 and -1 from the star; planets
+    first gives -1 + 0.75 ulp -> rounds to -(1 - 2^-53); star first rounds
+    each small term away and gives exactly -1."""
+    u = 2.0 ** -53
+    m = np.array([1.0, 1.0, 6 * u, 24 * u])
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [5.0, 0, 0], [9.0, 0, 0]])
+    v = np.zeros((4, 3))
+    a, _ = ora.accjerk(m, x, v)
+    assert a[1, 0] == -(1.0 - u)
+
+
+# --------------------------------------------------------------------------
+# Invariants and symmetry
+# --------------------------------------------------------------------------
+def _three_body_system(seed=0):
+    from paper_1208_1157_amd import gen
+    ens = gen.three_body(4, seed)
+    return ens.system(seed % 4)
+
+
+def test_time_reversal_pec2(ora):
+    m, x, v = _three_body_system()
+    h = 2 * math.pi / 1000
+    xf, vf, af, jf = ora.integrate_fixed(m, x, v, h, 1000)
+    xb, vb, _, _ = ora.integrate_fixed(m, xf, vf, -h, 1000, acc=af, jerk=jf)
+    assert np.abs(xb - x).max() < 1e-11
+    assert np.abs(vb - v).max() < 1e-11
+
+
+def test_time_reversal_converged(ora):
+    m, x, v = _three_body_system(1)
+    h = 2 * math.pi / 500
+    xf, vf, _, _ = ora.integrate_fixed(m, x, v, h, 500, converged=True)
+    xb, vb, _, _ = ora.integrate_fixed(m, xf, vf, -h, 500, converged=True)
+    assert np.abs(xb - x).max() < 1e-13
+    assert np.abs(vb - v).max() < 1e-13
+
+
+def test_energy_angmom_closed_form_two_body(ora):
+    m0, m1, a = 1.0, 3e-3, 1.7
+    x, v = kepler.two_body_state(m0, m1, a, 0.0, 0.0)
+    E, L = ora.energy(np.array([m0, m1]), x, v)
+    mu = m0 + m1
+    assert abs(E - (-m0 * m1 / (2 * a))) < 1e-16
+    assert abs(L[2] - (m0 * m1 / mu) * math.sqrt(mu * a)) < 1e-16
+    assert L[0] == 0 and L[1] == 0
+
+
+def test_energy_conserved_and_scales_h4(ora):
+    m, x, v = _three_body_system(2)
+    E0, L0 = ora.energy(m, x, v)
+    errs = []
+    for N in (500, 1000):
+        xf, vf, _, _ = ora.integrate_fixed(m, x, v, 2 * math.pi * 3 / N / 3, N * 3 // 3)
+        E1, L1 = ora.energy(m, xf, vf)
+        errs.append(abs((E1 - E0) / E0))
+        assert np.abs(L1 - L0).max() < 1e-12 * np.abs(L0).max()
+    assert errs[0] < 1e-9
+    assert errs[1] < errs[0] / 8
+
+
+def test_momentum_conserved_along_integration(ora):
+    m, x, v = _three_body_system(3)
+    p0 = (m[:, None] * v).sum(0)
+    _, vf, _, _ = ora.integrate_fixed(m, x, v, 2 * math.pi / 1000, 2000)
+    p1 = (m[:, None] * vf).sum(0)
+    assert np.abs(p1 - p0).max() < 1e-16
+
+
+def test_rotation_and_galilean_covariance(ora):
+    m, x, v = _three_body_system(0)
+    Q, _ = np.linalg.qr(np.random.default_rng(5).normal(size=(3, 3)))
+    shift_x, shift_v = np.array([3.0, -1.0, 0.5]), np.array([0.1, 0.2, -0.3])
+    h, N = 2 * math.pi / 1000, 500
+    xf, vf, _, _ = ora.integrate_fixed(m, x, v, h, N)
+    xr, vr, _, _ = ora.integrate_fixed(m, x @ Q.T, v @ Q.T, h, N)
+    assert np.abs(xr - xf @ Q.T).max() < 1e-12
+    xg, vg, _, _ = ora.integrate_fixed(m, x + shift_x, v + shift_v, h, N)
+    assert np.abs(xg - (xf + shift_x + shift_v * N * h)).max() < 1e-12
+    assert np.abs(vg - (vf + shift_v)).max() < 1e-12
+
+
+def test_planet_permutation_changes_only_roundoff(ora):
+    from paper_1208_1157_amd import gen
+    ens = gen.ragged_hill(8, 11, n_lo=6, n_hi=6)
+    m, x, v = ens.system(0)
+    perm = np.array([0, 3, 1, 5, 2, 4])
+    h, N = 2 * math.pi / 2000, 1000
+    xf, vf, _, _ = ora.integrate_fixed(m, x, v, h, N)
+    xp, vp, _, _ = ora.integrate_fixed(m[perm], x[perm], v[perm], h, N)
+    assert np.abs(xp - xf[perm]).max() < 1e-12
+
+
+def test_extra_evaluation_option_converges_to_same_orbit(ora):
+    """P(EC)^3 and the converged corrector agree with P(EC)^2 to truncation level."""
+    m, x, v = _three_body_system(1)
+    h, N = 2 * math.pi / 1000, 1000
+    x2, _, _, _ = ora.integrate_fixed(m, x, v, h, N, n_corr=2)
+    x3, _, _, _ = ora.integrate_fixed(m, x, v, h, N, n_corr=3)
+    xc, _, _, _ = ora.integrate_fixed(m, x, v, h, N, converged=True)
+    assert np.abs(x2 - x3).max() < 1e-9
+    assert np.abs(x3 - xc).max() < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Adaptive step rule and stop rules (readings; closed forms where they exist)
+# --------------------------------------------------------------------------
+def test_pair_timestep_closed_form(ora):
+    """|a_ij|/|j_ij| = r / sqrt(u_t^2 + 4 u_r^2) for the two-body relative orbit."""
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        m = np.array([1.0, rng.uniform(1e-5, 1e-2)])
+        x = rng.normal(size=(2, 3))
+        v = rng.normal(size=(2, 3))
+        r = x[1] - x[0]
+        u = v[1] - v[0]
+        rn = np.linalg.norm(r)
+        ur = (r @ u) / rn
+        ut2 = u @ u - ur * ur
+        expect = 0.01 * rn / math.sqrt(ut2 + 4 * ur * ur)
+        assert abs(ora.pair_timestep(m, x, v, 0.01) - expect) < 1e-13 * expect
+
+
+def test_pair_timestep_takes_minimum_over_pairs(ora):
+    m = np.array([1.0, 1e-3, 1e-3])
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, 5.0, 0]])
+    v = np.array([[0.0, 0, 0], [0, 1.0, 0], [-0.5, 0, 0]])
+    # pair (0,1): r=1, u=(0,1,0) tangential -> 1/1; others larger
+    assert abs(ora.pair_timestep(m, x, v, 1.0) - 1.0) < 1e-15
+
+
+def test_stop_rules(ora):
+    m = np.array([1.0, 1e-3, 1e-3])
+    v = np.zeros((3, 3))
+    hill = (2e-3 / 3.0) ** (1.0 / 3.0) * 1.0   # (r_i + r_j)/2 = 1
+    x = np.array([[0.0, 0, 0], [1.0, 0.5 * hill * 0.999, 0], [1.0, -0.5 * hill * 0.999, 0]])
+    # separations: r_i slightly above 1, so the Hill radius is slightly above `hill`
+    assert ora.check_stop(m, x, v, 3, 100.0) == ora.ENCOUNTER
+    x2 = np.array([[0.0, 0, 0], [1.0, 0, 0], [1.0, 1.5 * hill, 0]])
+    assert ora.check_stop(m, x2, v, 3, 100.0) == ora.ACTIVE
+    assert ora.check_stop(m, x, v, 2, 100.0) == ora.ACTIVE   # encounter rule off
+    x3 = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, 100.5, 0]])
+    assert ora.check_stop(m, x3, v, 3, 100.0) == ora.EJECTED
+    x4 = x3.copy(); x4[1, 2] = np.nan
+    assert ora.check_stop(m, x4, v, 3, 100.0) == ora.NONFINITE
+
+
+def test_adaptive_hyperbolic_planet_is_ejected(ora):
+    m = np.array([1.0, 1e-5, 1e-5])
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, 3.0, 0]])
+    v = np.array([[0.0, 0, 0], [0, 1.0, 0], [2.0, 0.0, 0]])   # escape speed at r=3 is 0.82
+    out = ora.integrate_adaptive(m, x, v, t_end=1e4, eta=0.01)
+    assert out["status"] == ora.EJECTED
+    r = np.linalg.norm(out["pos"][2] - out["pos"][0])
+    assert 100.0 < r < 100.0 + 2.0 * out["dt_next"] / 0.01 * 0.05 + 5.0
+
+
+def test_adaptive_lands_on_t_end_and_conserves_energy(ora):
+    m, x, v = _three_body_system(0)
+    E0, _ = ora.energy(m, x, v)
+    out = ora.integrate_adaptive(m, x, v, t_end=2 * math.pi * 5.37, eta=0.01)
+    assert out["status"] == ora.DONE
+    assert out["t"] == 2 * math.pi * 5.37
+    E1, _ = ora.energy(m, out["pos"], out["vel"])
+    assert abs((E1 - E0) / E0) < 1e-9
+
+
+def test_adaptive_two_body_matches_kepler(ora):
+    m0, m1, a, e = 1.0, 1e-3, 1.0, 0.3
+    x, v = kepler.two_body_state(m0, m1, a, e, 0.0)
+    T = 2 * math.pi * 2.5
+    out = ora.integrate_adaptive(np.array([m0, m1]), x, v, t_end=T, eta=0.005)
+    xe, ve = kepler.two_body_state(m0, m1, a, e, T)
+    assert out["status"] == ora.DONE
+    assert np.abs(out["pos"] - xe).max() < 1e-8
+
+
+def test_close_encounter_detected_at_first_step(ora):
+    """Two planets on a collision course: the flag is raised at the first
+    committed step whose state satisfies the criterion (checked step by step
+    with the single-step check routine)."""
+    m = np.array([1.0, 1e-4, 1e-4])
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [1.0, 0.2, 0]])
+    v = np.array([[0.0, 0, 0], [0, 1.0, 0], [0, 0.5, 0]])
+    out = ora.integrate_adaptive(m, x, v, t_end=10.0, eta=0.01)
+    assert out["status"] == ora.ENCOUNTER
+    steps = out["steps"]
+    prev = ora.integrate_adaptive(m, x, v, t_end=10.0, eta=0.01, max_steps=steps - 1)
+    assert prev["status"] == ora.MAXSTEPS
+    assert ora.check_stop(m, prev["pos"], prev["vel"], 3, 100.0) == ora.ACTIVE
+    assert ora.check_stop(m, out["pos"], out["vel"], 3, 100.0) == ora.ENCOUNTER
+
+
+def test_ensemble_driver_equals_single_system_calls(ora):
+    from paper_1208_1157_amd import gen
+    ens = gen.ragged_hill(20, 5, n_lo=3, n_hi=9)
+    h, N = 2 * math.pi / 2000, 50
+    X, V, A, J = ora.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, h, N, nthreads=3)
+    off = ens.offsets
+    for s in range(ens.n_sys):
+        m, x, v = ens.system(s)
+        xs, vs, as_, js = ora.integrate_fixed(m, x, v, h, N)
+        sl = slice(off[s], off[s + 1])
+        assert np.array_equal(X[sl], xs) and np.array_equal(V[sl], vs)
+        assert np.array_equal(A[sl], as_) and np.array_equal(J[sl], js)
