@@ -1,0 +1,210 @@
+/*
+ * fewbody.h -- C ABI of libfewbody: FP64 fourth-order time-symmetrised
+ * Hermite P(EC)^2 integration of very many independent few-body systems on
+ * one AMD MI355X (gfx950).
+ *
+ * The method is the Hermite predictor-corrector of the Swarm-NG paper
+ * (arXiv:1208.1157): Newtonian pair acceleration with G = 1 (Section 2.1,
+ * Eq. 1) and its analytic time derivative (the jerk, Section 2.2.1), the
+ * predictor of Eq. 3, the corrector of Eq. 4 applied twice per step
+ * (Algorithm 2), inside the many-steps-per-launch loop of Algorithm 1.
+ * Eq. 4 is read with coefficient 3/20, a (dt)^3 jerk term and the predicted
+ * state as the base of every correction; the step's last evaluation is
+ * carried as the next step's (a0, j0).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Ensembles are ragged: system s has n_body[s] bodies (2..FB_MAX_BODIES);
+ * body 0 of each system is its central star (only the stop rules care).
+ * Flat body arrays are body-major: body b of system s is row off[s] + b with
+ * off the exclusive prefix sum of n_body; pos/vel/acc/jerk rows hold x,y,z.
+ * All floating point is IEEE binary64.
+ *
+ * Errors: every call returns an fb_status; FB_OK is 0 and every error is
+ * negative.  fb_last_error() returns a thread-local message for the most
+ * recent failure.  No C++ exception crosses this interface.
+ *
+ * Ownership: the caller keeps every buffer it passes; the library copies
+ * inputs during the call and never frees or retains caller memory, except
+ * the workspace of fb_ensemble_create_device, which must outlive the
+ * ensemble.  Streams are borrowed (NULL = the null stream).  Work is
+ * enqueued asynchronously on the ensemble's stream; fb_get_* calls and
+ * fb_diagnostics synchronise that stream before they return.
+ *
+ * Run-time failures of a single system (non-finite state, e.g. coincident
+ * bodies) mark that system's status and never fail the call.
+ */
+#ifndef FEWBODY_H
+#define FEWBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FB_MAX_BODIES 16
+
+typedef enum {
+    FB_OK = 0,
+    FB_E_INVAL = -1,     /* bad argument (message says which)               */
+    FB_E_NOMEM = -2,     /* device allocation failed / workspace too small  */
+    FB_E_DEVICE = -3,    /* HIP runtime error                               */
+    FB_E_BUDGET = -4,    /* serving: request exceeds the server's budget    */
+    FB_E_STATE = -5,     /* call not valid in the object's current state    */
+    FB_E_NOTFOUND = -6   /* serving: unknown request id                     */
+} fb_status;
+
+/* Per-system status codes. */
+enum {
+    FB_SYS_ACTIVE = 0,     /* still integrating                               */
+    FB_SYS_DONE = 1,       /* reached the destination time / step count       */
+    FB_SYS_ENCOUNTER = 2,  /* two planets closer than one mutual Hill radius  */
+    FB_SYS_EJECTED = 3,    /* a planet farther than r_eject from its star     */
+    FB_SYS_NONFINITE = 4,  /* a position or velocity became NaN or infinite   */
+    FB_SYS_STALLED_DT = 5, /* adaptive step fell below 1e-12 * |t_end|        */
+    FB_SYS_MAXSTEPS = 6    /* hit fb_opts.max_steps                           */
+};
+
+/* Stop-rule bits for fb_opts.stop_rules. */
+enum { FB_STOP_ENCOUNTER = 1, FB_STOP_EJECT = 2 };
+
+/* Lane mappings of a launch plan. */
+enum {
+    FB_MAP_AUTO = 0,             /* use the plan table                         */
+    FB_MAP_SYSTEM_PER_LANE = 1,  /* one system per lane, all state in VGPRs    */
+    FB_MAP_BODY_PER_LANE = 2     /* one body per lane, partners through LDS    */
+};
+
+/* Schedules. */
+enum {
+    FB_SCHED_PLAIN = 0,       /* one launch per homogeneous body-count bucket  */
+    FB_SCHED_PERSISTENT = 1   /* one fused persistent launch over all buckets,
+                                 tiles pulled longest-first from a queue        */
+};
+
+/* Integration options; NULL means all defaults.  Defaults: fixed step, no
+ * stop rules, eta 0.01, r_eject 100, max_steps unlimited, plain schedule,
+ * one quantum for the whole run, no compaction. */
+typedef struct {
+    int32_t adaptive;           /* 0: fixed dt.  1: per-system adaptive step
+                                   dt = eta * min over pairs |a_ij|/|j_ij| of
+                                   the pair's two-body relative acceleration and
+                                   jerk at the step's last evaluation (the
+                                   set-up evaluation for the first step); the
+                                   final step is shortened to land on t_end.    */
+    double eta;                 /* adaptive accuracy parameter                  */
+    int32_t stop_rules;         /* FB_STOP_* bits, checked after every step     */
+    double r_eject;             /* ejection radius from the star                */
+    int64_t max_steps;          /* per-system cap on steps (<=0: unlimited)     */
+    int32_t schedule;           /* FB_SCHED_*                                   */
+    int32_t steps_per_quantum;  /* persistent schedule: steps per launch
+                                   (<=0: whole run in one launch)               */
+    int32_t compact;            /* persistent schedule: rebuild tiles from the
+                                   still-active systems after every quantum     */
+} fb_opts;
+
+/* Fill *o with the defaults above. */
+void fb_opts_default(fb_opts *o);
+
+/* ---------------------------------------------------------------- ensembles */
+typedef struct fb_ensemble fb_ensemble;
+
+/* Create an ensemble from HOST arrays (Section 2.1's state: masses,
+ * positions, velocities of every body of every system).
+ *   n_sys      number of systems (>= 0)
+ *   n_body     [n_sys] bodies per system, 2..FB_MAX_BODIES
+ *   mass       [N] >= 0 and finite;  pos, vel [N][3] finite;  N = sum n_body
+ *   t0         [n_sys] start times, or NULL for all zero
+ *   hip_stream hipStream_t to enqueue on (borrowed), NULL = null stream
+ * The library allocates and owns the device state.  The set-up evaluation
+ * of (a0, j0) (Algorithm 1's "prepare") runs here.  Returns FB_E_INVAL on
+ * bad input, FB_E_NOMEM / FB_E_DEVICE on HIP failures. */
+fb_status fb_ensemble_create(int32_t n_sys, const int32_t *n_body,
+                             const double *mass, const double *pos,
+                             const double *vel, const double *t0,
+                             void *hip_stream, fb_ensemble **out);
+
+/* Bytes of device workspace an ensemble of this shape needs. */
+size_t fb_workspace_bytes(int32_t n_sys, const int32_t *n_body);
+
+/* Same as fb_ensemble_create, but mass/pos/vel/t0 are DEVICE pointers (t0
+ * may be NULL) and all device state lives in the caller's workspace of
+ * ws_bytes >= fb_workspace_bytes(...) bytes, 256-byte aligned.  The caller
+ * owns the workspace (e.g. a torch tensor) and keeps it alive until
+ * fb_ensemble_destroy; n_body stays a host array.  Input values are
+ * validated on the device; a bad value fails the call with FB_E_INVAL. */
+fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body,
+                                    const double *d_mass, const double *d_pos,
+                                    const double *d_vel, const double *d_t0,
+                                    void *d_workspace, size_t ws_bytes,
+                                    void *hip_stream, fb_ensemble **out);
+
+/* Advance every active system by exactly n_steps fixed steps of size dt
+ * (dt may be negative: backward integration).  Times become
+ * t_start + n_steps * dt.  o: schedule/quantum/stop options (o->adaptive
+ * must be 0); NULL = defaults. */
+fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
+                             const fb_opts *o);
+
+/* Integrate every active system to t_end (Algorithm 1's destination time).
+ * Fixed step (o->adaptive == 0): whole steps of dt, then one shortened step
+ * that lands on t_end (skipped when the remainder is below 1e-9 |dt|); the
+ * sign of dt must match t_end - t.  Adaptive: dt is ignored; forward only.
+ * Systems whose status is not ACTIVE/DONE (stopped by a rule) stay put. */
+fb_status fb_integrate(fb_ensemble *e, double t_end, double dt,
+                       const fb_opts *o);
+
+/* Wait for all work enqueued on the ensemble's stream. */
+fb_status fb_synchronize(fb_ensemble *e);
+
+/* Copy state to HOST arrays in the caller's system order; any pointer may be
+ * NULL to skip it.  pos, vel [N][3]; t [n_sys]; status [n_sys] (FB_SYS_*);
+ * steps [n_sys] = steps taken since creation. */
+fb_status fb_get_state(fb_ensemble *e, double *pos, double *vel, double *t,
+                       int32_t *status, int64_t *steps);
+
+/* Checkpoint part of the state: the carried (a0, j0) of every body, [N][3]
+ * each, and each system's carried adaptive step (dt_next, [n_sys]); any
+ * pointer may be NULL. */
+fb_status fb_get_hermite_state(fb_ensemble *e, double *acc0, double *jerk0,
+                               double *dt_next);
+
+/* Energy (Eq. 6 with each pair counted once) and angular momentum about the
+ * origin (sum of m x cross v) of every system, computed on the device; only
+ * these 4 doubles per system cross to the HOST arrays energy [n_sys] and
+ * angmom [n_sys][3] (either may be NULL). */
+fb_status fb_diagnostics(fb_ensemble *e, double *energy, double *angmom);
+
+/* Number of systems and total bodies. */
+fb_status fb_ensemble_shape(const fb_ensemble *e, int32_t *n_sys, int64_t *n_bodies);
+
+fb_status fb_ensemble_destroy(fb_ensemble *e);
+
+/* ---------------------------------------------------------------- plans */
+/* The launch plan of body count n: lane mapping (FB_MAP_*), waves per
+ * workgroup (1..16), and, for the persistent schedule, workgroups per CU
+ * (1..32).  Plans are process-wide; the autotuner sets them. */
+fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group,
+                      int32_t groups_per_cu);
+fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
+                      int32_t *groups_per_cu);
+
+/* ---------------------------------------------------------------- timing */
+/* When enabled, the library brackets each integration kernel it launches
+ * with HIP events on the ensemble's stream and accumulates their elapsed
+ * time; fb_profile_read synchronises and returns (total ms, launches) since
+ * the last reset. */
+fb_status fb_profile_enable(int32_t on);
+fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
+
+/* ---------------------------------------------------------------- misc */
+const char *fb_last_error(void);
+const char *fb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEWBODY_H */

@@ -1,0 +1,105 @@
+// Internal types shared by the HIP kernels (fb_kernels.hip) and the host
+// runtime (fb_runtime.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fb {
+
+// Rows of a bucket's structure-of-arrays state; row r, body b, slot s lives
+// at st[(r * n + b) * pitch + s] (slot fastest: lanes read consecutive
+// doubles).  a0/j0 are the carried acceleration and jerk of the step's last
+// evaluation.
+enum Row { R_M = 0, R_X = 1, R_V = 4, R_A = 7, R_J = 10, R_COUNT = 13 };
+
+enum SysStatus {
+    ST_ACTIVE = 0, ST_DONE = 1, ST_ENCOUNTER = 2, ST_EJECTED = 3,
+    ST_NONFINITE = 4, ST_STALLED = 5, ST_MAXSTEPS = 6
+};
+
+enum Mapping { MAP_SPL = 1, MAP_BPL = 2 };
+
+constexpr int kMaxBodies = 16;
+constexpr int kMaxSplBodies = 6;       // plain system-per-lane instances exist for n <= 6
+constexpr int kMaxSplPersistent = 3;   // ... and inside the fused persistent kernel for n <= 3
+
+// Device view of one homogeneous body-count bucket.  Per-slot arrays have
+// `pitch` entries; slots [0, count) hold systems.
+struct Bucket {
+    double *st;          // [R_COUNT][n][pitch]
+    double *t;           // current time
+    double *t_end;       // destination time of the current run
+    double *dt;          // fixed step of the current run
+    double *dtn;         // carried adaptive step (<= 0: not yet proposed)
+    double *t0run;       // time at the start of the current run
+    long long *krun;     // whole steps taken in the current run
+    long long *nfull;    // whole steps the current run takes before t_end
+    long long *steps;    // steps since creation
+    int *status;         // SysStatus
+    int *orig;           // caller's index of the system in each slot
+    int n, pitch, count, pad;
+};
+
+// One unit of persistent-schedule work: `count` systems of bucket `bucket`
+// starting at `first` (a slot, or an index into an active list).
+struct Tile {
+    int bucket, first, count, kind;   // kind = mapping * 32 + n
+};
+
+struct StepParams {
+    int adaptive;        // 0 fixed step, 1 adaptive step rule
+    int stop_rules;      // bit 0 close encounter, bit 1 ejection
+    double eta;
+    double r_eject;
+    long long max_steps; // per-system cap (LLONG_MAX: none)
+    int quantum;         // at most this many steps per system per launch
+    int pad;
+};
+
+// Compaction bookkeeping for the persistent schedule (device memory).
+struct ActiveLists {
+    int *cur;            // [sum pitch] active slots of each bucket, by bucket base
+    int *next;           // survivors written by the running quantum
+    int *base;           // [n_buckets] offset of each bucket's list
+    int *cur_count;      // [n_buckets]
+    int *next_count;     // [n_buckets]
+};
+
+inline int spl_tile_systems() { return 64; }
+inline int bpl_tile_systems(int n) { return 64 / n; }
+inline int tile_systems(int mapping, int n) {
+    return mapping == MAP_SPL ? spl_tile_systems() : bpl_tile_systems(n);
+}
+
+// ---- launchers (fb_kernels.hip) -------------------------------------------
+hipError_t launch_pack(const Bucket &B, const double *mass, const double *pos,
+                       const double *vel, const double *t0,
+                       const long long *orig_off, int *bad, hipStream_t s);
+hipError_t launch_prepare(const Bucket &B, hipStream_t s);
+hipError_t launch_begin_run(const Bucket &B, int fixed_steps, long long n_steps,
+                            double t_end, double dt, int adaptive, double eta,
+                            hipStream_t s);
+hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group,
+                        const StepParams &P, hipStream_t s);
+hipError_t launch_persistent(const Bucket *d_buckets, const Tile *d_tiles,
+                             const int *d_ntiles, int *d_head, const int *d_lists,
+                             const StepParams &P, int adv, int grid,
+                             int waves_per_group, ActiveLists *compact,
+                             hipStream_t s);
+hipError_t launch_build_tiles(const Bucket *d_buckets, int n_buckets,
+                              const int *d_order, const int *d_mapping,
+                              ActiveLists L, Tile *d_tiles, int *d_ntiles,
+                              int *d_head, hipStream_t s);
+hipError_t launch_reset_counter(int *p, int n, hipStream_t s);
+hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos,
+                         double *vel, double *acc, double *jerk, double *t,
+                         int *status, long long *steps, double *dt_next,
+                         hipStream_t s);
+hipError_t launch_diag(const Bucket &B, double *energy, double *angmom,
+                       hipStream_t s);
+hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s);
+size_t persistent_lds_bytes(int waves_per_group);
+int persistent_max_groups_per_cu(int adv, int waves_per_group);
+
+}  // namespace fb

@@ -1,0 +1,1230 @@
+// fb_kernels.hip -- gfx950 kernels of libfewbody.
+//
+// FP64 fourth-order time-symmetrised Hermite P(EC)^2 steps of many
+// independent few-body systems (Swarm-NG, arXiv:1208.1157: Eq. 1 and its
+// time derivative for the pair forces, Eq. 3 predictor, Eq. 4 corrector
+// applied twice per step as in Algorithm 2, many steps per launch as in
+// Algorithm 1).  All arithmetic is FP64 on the vector ALUs; the pair sums are
+// not a dense contraction, so no MFMA is used.
+//
+// Two lane mappings (both read the bucket's structure-of-arrays state with
+// consecutive lanes on consecutive slots):
+//   SPL  one system per lane.  The whole system lives in VGPRs for the whole
+//        step loop; every pair is evaluated once (Newton's third law), no
+//        cross-lane traffic.  Used for small n.
+//   BPL  one body per lane, floor(64/n) systems per wavefront (lane = body *
+//        S + system).  Each lane evaluates its body's n-1 interactions with
+//        partner positions/velocities read from the wave's LDS slice; no
+//        reduction is needed and every lane does useful work.
+// In both, each body sums its planet partners in ascending order and the
+// star last (Section 4.2).
+//
+// The corrector uses the algebraically equivalent "x0 form" of Eq. 4 (read
+// with coefficient 3/20, a (dt)^3 jerk term and the predicted state as
+// base): v1 = v0 + h/2 (a0 + a1) + h^2/12 (j0 - j1),
+// x1 = x0 + h/2 (v0 + v1) + h^2/10 (a0 - a1) + h^3/120 (j0 + j1),
+// with the a0/j0 parts folded into per-step bases so each correction costs
+// five FMAs per component.
+#include "fb_internal.h"
+
+#include <climits>
+
+// Partner-loop unroll of the body-per-lane evaluation: full unrolling lets
+// the scheduler hoist every partner's LDS loads and costs occupancy.
+#ifndef FB_BPL_UNROLL
+#define FB_BPL_UNROLL 2
+#endif
+// Waves per SIMD the register allocator targets for the body-per-lane and
+// persistent kernels.
+#ifndef FB_BPL_WAVES
+#define FB_BPL_WAVES 4
+#endif
+
+namespace fb {
+namespace {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+// LDS exchange among the lanes of one wavefront: order this wave's LDS
+// writes before its subsequent reads (no workgroup barrier needed: every
+// exchange stays inside one wavefront's slice).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1/sqrt(x): hardware estimate (v_rsq_f64) refined by two Newton-Raphson
+// steps y <- y + (y/2)(1 - x y^2), which converge quadratically from the
+// estimate's error to FP64 rounding level.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    return y;
+}
+
+__device__ __forceinline__ bool finite3(const double (&p)[3])
+{
+    return __builtin_isfinite(p[0]) && __builtin_isfinite(p[1]) && __builtin_isfinite(p[2]);
+}
+
+// Step coefficients of the predictor (Eq. 3) and corrector (Eq. 4).
+struct Coef {
+    double h, hh2, hhh6;       // h, h^2/2, h^3/6
+    double c1, c2, c3, c4;     // h/2, h^2/12, h^2/10, h^3/120
+};
+
+__device__ __forceinline__ Coef make_coef(double h)
+{
+    Coef k;
+    const double h2 = h * h, h3 = h2 * h;
+    k.h = h;
+    k.hh2 = 0.5 * h2;
+    k.hhh6 = h3 * (1.0 / 6.0);
+    k.c1 = 0.5 * h;
+    k.c2 = h2 * (1.0 / 12.0);
+    k.c3 = h2 * 0.1;
+    k.c4 = h3 * (1.0 / 120.0);
+    return k;
+}
+
+// Predicted state and the per-step bases of the corrector for one component.
+__device__ __forceinline__ void predict_comp(const Coef &k, double x, double v, double a,
+                                             double j, double &xp, double &vp, double &bx,
+                                             double &bv)
+{
+    xp = fma(k.hhh6, j, fma(k.hh2, a, fma(k.h, v, x)));
+    vp = fma(k.hh2, j, fma(k.h, a, v));
+    bx = fma(k.c4, j, fma(k.c3, a, fma(k.c1, v, x)));
+    bv = fma(k.c2, j, fma(k.c1, a, v));
+}
+
+// One correction of one component from the latest evaluation (ak, jk).
+__device__ __forceinline__ void correct_comp(const Coef &k, double bx, double bv, double ak,
+                                             double jk, double &xc, double &vc)
+{
+    vc = fma(-k.c2, jk, fma(k.c1, ak, bv));
+    xc = fma(k.c4, jk, fma(-k.c3, ak, fma(k.c1, vc, bx)));
+}
+
+// ---------------------------------------------------------------------------
+// per-system clock (Algorithm 1's loop control)
+// ---------------------------------------------------------------------------
+struct Clock {
+    double t, t_end, dt, dtn, t0;
+    long long k, nfull, steps;
+    int status;
+};
+
+__device__ __forceinline__ Clock load_clock(const Bucket &B, int s)
+{
+    Clock c;
+    c.t = B.t[s];
+    c.t_end = B.t_end[s];
+    c.dt = B.dt[s];
+    c.dtn = B.dtn[s];
+    c.t0 = B.t0run[s];
+    c.k = B.krun[s];
+    c.nfull = B.nfull[s];
+    c.steps = B.steps[s];
+    c.status = B.status[s];
+    return c;
+}
+
+__device__ __forceinline__ void store_clock(const Bucket &B, int s, const Clock &c)
+{
+    B.t[s] = c.t;
+    B.dtn[s] = c.dtn;
+    B.krun[s] = c.k;
+    B.steps[s] = c.steps;
+    B.status[s] = c.status;
+}
+
+// Size of the next step, or false (with the status updated) if the system
+// takes no further step.
+__device__ __forceinline__ bool plan_step(Clock &c, const StepParams &P, double &h, bool &last)
+{
+    if (c.status != ST_ACTIVE)
+        return false;
+    if (P.adaptive) {
+        if (!(c.t < c.t_end)) {
+            c.status = ST_DONE;
+            return false;
+        }
+        if (c.steps >= P.max_steps) {
+            c.status = ST_MAXSTEPS;
+            return false;
+        }
+        if (__builtin_isnan(c.dtn)) {
+            c.status = ST_NONFINITE;
+            return false;
+        }
+        if (!(c.dtn >= 1e-12 * fabs(c.t_end))) {
+            c.status = ST_STALLED;
+            return false;
+        }
+        last = c.t + c.dtn >= c.t_end;
+        h = last ? c.t_end - c.t : c.dtn;
+        return true;
+    }
+    if (c.steps >= P.max_steps) {
+        c.status = ST_MAXSTEPS;
+        return false;
+    }
+    if (c.k < c.nfull) {
+        h = c.dt;
+        last = false;
+        return true;
+    }
+    const double rem = c.t_end - c.t;
+    if (rem * c.dt > 1e-9 * c.dt * c.dt) {   // remainder in the direction of dt
+        h = rem;
+        last = true;
+        return true;
+    }
+    c.t = c.t_end;
+    c.status = ST_DONE;
+    return false;
+}
+
+__device__ __forceinline__ void finish_step(Clock &c, const StepParams &P, bool last, double h,
+                                            double dt_prop)
+{
+    c.steps += 1;
+    if (P.adaptive) {
+        c.t = last ? c.t_end : c.t + h;
+        c.dtn = dt_prop;
+        if (last)
+            c.status = ST_DONE;
+        return;
+    }
+    if (last) {
+        c.t = c.t_end;
+        c.status = ST_DONE;
+        return;
+    }
+    c.k += 1;
+    c.t = fma((double)c.k, c.dt, c.t0);
+    if (c.k >= c.nfull) {
+        const double rem = c.t_end - c.t;
+        if (!(rem * c.dt > 1e-9 * c.dt * c.dt)) {
+            c.t = c.t_end;
+            c.status = ST_DONE;
+        }
+    }
+}
+
+__device__ __forceinline__ int status_of_flags(int fl)
+{
+    return (fl & 1) ? ST_NONFINITE : (fl & 2) ? ST_ENCOUNTER : (fl & 4) ? ST_EJECTED : ST_ACTIVE;
+}
+
+// ---------------------------------------------------------------------------
+// system-per-lane (SPL)
+// ---------------------------------------------------------------------------
+
+// Pair (i, j): r = x_j - x_i, u = v_j - v_i, A = r/|r|^3,
+// J = u/|r|^3 - 3 (r.u)/|r|^2 A; body i gains m_j (A, J), body j loses
+// m_i (A, J).  With TS, also track max over pairs of
+// (|u|^2 + 3 (r.u)^2/|r|^2) / |r|^2 = (|j_ij| / |a_ij|)^2 of the pair's
+// two-body relative motion (the step rule's quantity).
+template <int N, bool TS>
+__device__ __forceinline__ void spl_pair(const int i, const int j, const double (&m)[N],
+                                         const double (&x)[N][3], const double (&v)[N][3],
+                                         double (&a)[N][3], double (&jk)[N][3], double &wmax)
+{
+    const double rx = x[j][0] - x[i][0], ry = x[j][1] - x[i][1], rz = x[j][2] - x[i][2];
+    const double ux = v[j][0] - v[i][0], uy = v[j][1] - v[i][1], uz = v[j][2] - v[i][2];
+    const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+    const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
+    const double ri = rsqrt_nr(r2);
+    const double ri2 = ri * ri;
+    const double ri3 = ri2 * ri;
+    const double al = 3.0 * ru * ri2;
+    const double Ax = rx * ri3, Ay = ry * ri3, Az = rz * ri3;
+    const double Jx = fma(-al, Ax, ux * ri3), Jy = fma(-al, Ay, uy * ri3), Jz = fma(-al, Az, uz * ri3);
+    a[i][0] = fma(m[j], Ax, a[i][0]);
+    a[i][1] = fma(m[j], Ay, a[i][1]);
+    a[i][2] = fma(m[j], Az, a[i][2]);
+    a[j][0] = fma(-m[i], Ax, a[j][0]);
+    a[j][1] = fma(-m[i], Ay, a[j][1]);
+    a[j][2] = fma(-m[i], Az, a[j][2]);
+    jk[i][0] = fma(m[j], Jx, jk[i][0]);
+    jk[i][1] = fma(m[j], Jy, jk[i][1]);
+    jk[i][2] = fma(m[j], Jz, jk[i][2]);
+    jk[j][0] = fma(-m[i], Jx, jk[j][0]);
+    jk[j][1] = fma(-m[i], Jy, jk[j][1]);
+    jk[j][2] = fma(-m[i], Jz, jk[j][2]);
+    if (TS) {
+        const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+        wmax = fmax(wmax, fma(al, ru, u2) * ri2);
+    }
+}
+
+// Acceleration and jerk of every body: planet-planet pairs first, then the
+// star's pairs, so each planet adds the star's contribution last.
+template <int N, bool TS>
+__device__ __forceinline__ void spl_accjerk(const double (&m)[N], const double (&x)[N][3],
+                                            const double (&v)[N][3], double (&a)[N][3],
+                                            double (&jk)[N][3], double &wmax)
+{
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a[b][c] = 0.0;
+            jk[b][c] = 0.0;
+        }
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+#pragma unroll
+        for (int j = i + 1; j < N; ++j)
+            spl_pair<N, TS>(i, j, m, x, v, a, jk, wmax);
+#pragma unroll
+    for (int j = 1; j < N; ++j)
+        spl_pair<N, TS>(0, j, m, x, v, a, jk, wmax);
+}
+
+// One P(EC)^2 step of size h.  On entry (a, jk) hold the carried a0, j0; on
+// exit (x, v) are the corrected state and (a, jk) the last evaluation.
+// Returns the step-rule quantity of the last evaluation (TS only).
+template <int N, bool TS>
+__device__ __forceinline__ double spl_step(const double (&m)[N], double (&x)[N][3],
+                                           double (&v)[N][3], double (&a)[N][3],
+                                           double (&jk)[N][3], double h)
+{
+    const Coef k = make_coef(h);
+    double bx[N][3], bv[N][3], xc[N][3], vc[N][3];
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            predict_comp(k, x[b][c], v[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c], bx[b][c],
+                         bv[b][c]);
+    double w = 0.0;
+    spl_accjerk<N, false>(m, xc, vc, a, jk, w);
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            correct_comp(k, bx[b][c], bv[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c]);
+    spl_accjerk<N, TS>(m, xc, vc, a, jk, w);
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            correct_comp(k, bx[b][c], bv[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c]);
+            x[b][c] = xc[b][c];
+            v[b][c] = vc[b][c];
+        }
+    return w;
+}
+
+// Stop-rule flags after a committed step: bit 0 non-finite, bit 1 two
+// planets within one mutual Hill radius, bit 2 a planet beyond r_eject.
+// The Hill test sep < ((m_i+m_j)/(3 m0))^(1/3) (r_i+r_j)/2 (r the astrocentric
+// distance) is evaluated without roots as
+// sep^6 < ((m_i+m_j)/(24 m0))^2 ((r_i+r_j)^2)^3.
+__device__ __forceinline__ bool hill_close(double sep2, double mi, double mj, double inv24m0,
+                                           double ri, double rj)
+{
+    const double mu = (mi + mj) * inv24m0;
+    const double w = (ri + rj) * (ri + rj);
+    return sep2 * sep2 * sep2 < mu * mu * (w * w * w);
+}
+
+template <int N>
+__device__ __forceinline__ int spl_stop_flags(const double (&m)[N], const double (&x)[N][3],
+                                              const double (&v)[N][3], const StepParams &P)
+{
+    bool fin = true;
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+        fin = fin && finite3(x[b]) && finite3(v[b]);
+    if (!fin)
+        return 1;
+    double r[N];
+    r[0] = 0.0;
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        const double dx = x[i][0] - x[0][0], dy = x[i][1] - x[0][1], dz = x[i][2] - x[0][2];
+        r[i] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    }
+    int fl = 0;
+    if (P.stop_rules & 1) {
+        const double inv24m0 = 1.0 / (24.0 * m[0]);
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+#pragma unroll
+            for (int j = i + 1; j < N; ++j) {
+                const double dx = x[i][0] - x[j][0], dy = x[i][1] - x[j][1],
+                             dz = x[i][2] - x[j][2];
+                const double sep2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (hill_close(sep2, m[i], m[j], inv24m0, r[i], r[j]))
+                    fl |= 2;
+            }
+    }
+    if (P.stop_rules & 2) {
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+            if (r[i] > P.r_eject)
+                fl |= 4;
+    }
+    return fl;
+}
+
+// Integrate one system (one lane) for at most P.quantum steps.
+template <int N, bool ADV>
+__device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
+{
+    Clock c = load_clock(B, slot);
+    if (c.status != ST_ACTIVE)
+        return;
+    const size_t pitch = B.pitch;
+    const double *st = B.st;
+    double m[N], x[N][3], v[N][3], a[N][3], jk[N][3];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        m[b] = st[(R_M * N + b) * pitch + slot];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            x[b][cc] = st[((R_X + cc) * N + b) * pitch + slot];
+            v[b][cc] = st[((R_V + cc) * N + b) * pitch + slot];
+            a[b][cc] = st[((R_A + cc) * N + b) * pitch + slot];
+            jk[b][cc] = st[((R_J + cc) * N + b) * pitch + slot];
+        }
+    }
+    for (int q = 0; q < P.quantum; ++q) {
+        double h = 0.0;
+        bool last = false;
+        if (!plan_step(c, P, h, last))
+            break;
+        const double w = spl_step<N, ADV>(m, x, v, a, jk, h);
+        const double dtp = ADV ? P.eta * rsqrt_nr(w) : 0.0;
+        finish_step(c, P, last, h, dtp);
+        if (ADV) {
+            const int fl = spl_stop_flags<N>(m, x, v, P);
+            if (fl)
+                c.status = status_of_flags(fl);
+        }
+        if (c.status != ST_ACTIVE)
+            break;
+    }
+    if (!ADV) {
+        bool fin = true;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+            fin = fin && finite3(x[b]) && finite3(v[b]);
+        if (!fin)
+            c.status = ST_NONFINITE;
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            B.st[((R_X + cc) * N + b) * pitch + slot] = x[b][cc];
+            B.st[((R_V + cc) * N + b) * pitch + slot] = v[b][cc];
+            B.st[((R_A + cc) * N + b) * pitch + slot] = a[b][cc];
+            B.st[((R_J + cc) * N + b) * pitch + slot] = jk[b][cc];
+        }
+    store_clock(B, slot, c);
+}
+
+// ---------------------------------------------------------------------------
+// body-per-lane (BPL)
+// ---------------------------------------------------------------------------
+
+// One wavefront's LDS slice: the current evaluation state of its 64 lanes
+// (as 16-byte pairs so a partner costs three ds_read_b128 and one b64),
+// the masses, and two reduction scratch rows.
+struct BplLds {
+    double2 xy[64];
+    double2 zvx[64];
+    double2 vyvz[64];
+    double m[64];
+    double red[64];
+    int redi[64];
+};
+
+// This wavefront's slice of the dynamic LDS of its workgroup.  Reached
+// through the module-level symbol (not passed as a pointer) so that code in
+// separately compiled tile functions still addresses LDS directly.
+__device__ __forceinline__ BplLds &wave_lds()
+{
+    extern __shared__ BplLds fb_dyn_lds[];
+    return fb_dyn_lds[threadIdx.x >> 6];
+}
+
+// k-th interaction partner of body b (0 <= k < n-1): the other planets in
+// ascending order, then the star (the star itself sums planets 1..n-1).
+template <int N>
+__device__ __forceinline__ int partner(const int k, const int b)
+{
+    if (b == 0)
+        return k + 1;
+    if (k == N - 2)
+        return 0;
+    return k + 1 + (k + 1 >= b ? 1 : 0);
+}
+
+// k-th planet partner of planet b (0 <= k < n-2).
+__device__ __forceinline__ int planet_partner(const int k, const int b)
+{
+    return k + 1 + (k + 1 >= b ? 1 : 0);
+}
+
+template <int N, bool TS>
+__device__ __forceinline__ void bpl_eval(BplLds &L, const int lane, const int b, const int s,
+                                         const double (&xi)[3], const double (&vi)[3],
+                                         double (&a)[3], double (&jk)[3], double &wmax)
+{
+    constexpr int S = 64 / N;
+    L.xy[lane] = make_double2(xi[0], xi[1]);
+    L.zvx[lane] = make_double2(xi[2], vi[0]);
+    L.vyvz[lane] = make_double2(vi[1], vi[2]);
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a[c] = 0.0;
+        jk[c] = 0.0;
+    }
+#pragma unroll FB_BPL_UNROLL
+    for (int k = 0; k < N - 1; ++k) {
+        const int idx = partner<N>(k, b) * S + s;
+        const double2 p0 = L.xy[idx];
+        const double2 p1 = L.zvx[idx];
+        const double2 p2 = L.vyvz[idx];
+        const double mj = L.m[idx];
+        const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
+        const double ux = p1.y - vi[0], uy = p2.x - vi[1], uz = p2.y - vi[2];
+        const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+        const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
+        const double ri = rsqrt_nr(r2);
+        const double ri2 = ri * ri;
+        const double mr3 = mj * (ri2 * ri);
+        const double al = 3.0 * ru * ri2;
+        a[0] = fma(mr3, rx, a[0]);
+        a[1] = fma(mr3, ry, a[1]);
+        a[2] = fma(mr3, rz, a[2]);
+        jk[0] = fma(mr3, fma(-al, rx, ux), jk[0]);
+        jk[1] = fma(mr3, fma(-al, ry, uy), jk[1]);
+        jk[2] = fma(mr3, fma(-al, rz, uz), jk[2]);
+        if (TS) {
+            const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+            wmax = fmax(wmax, fma(al, ru, u2) * ri2);
+        }
+    }
+    wave_sync();
+}
+
+template <int N>
+__device__ __forceinline__ double sys_max(BplLds &L, int lane, int s, double v)
+{
+    constexpr int S = 64 / N;
+    L.red[lane] = v;
+    wave_sync();
+    double r = L.red[s];
+#pragma unroll
+    for (int k = 1; k < N; ++k)
+        r = fmax(r, L.red[k * S + s]);
+    wave_sync();
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ int sys_or(BplLds &L, int lane, int s, int v)
+{
+    constexpr int S = 64 / N;
+    L.redi[lane] = v;
+    wave_sync();
+    int r = L.redi[s];
+#pragma unroll
+    for (int k = 1; k < N; ++k)
+        r |= L.redi[k * S + s];
+    wave_sync();
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const int b,
+                                              const int s, const double mi, const double (&x)[3],
+                                              const double (&v)[3], const StepParams &P)
+{
+    constexpr int S = 64 / N;
+    int fl = (finite3(x) && finite3(v)) ? 0 : 1;
+    L.xy[lane] = make_double2(x[0], x[1]);
+    L.zvx[lane] = make_double2(x[2], 0.0);
+    wave_sync();
+    const double2 s0 = L.xy[s];
+    const double2 s1 = L.zvx[s];
+    const double dx = x[0] - s0.x, dy = x[1] - s0.y, dz = x[2] - s1.x;
+    const double rb = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    L.red[lane] = rb;
+    wave_sync();
+    if (b >= 1) {
+        if ((P.stop_rules & 2) && rb > P.r_eject)
+            fl |= 4;
+        if (P.stop_rules & 1) {
+            const double inv24m0 = 1.0 / (24.0 * L.m[s]);
+#pragma unroll 1
+            for (int k = 0; k < N - 2; ++k) {
+                const int idx = planet_partner(k, b) * S + s;
+                const double2 q0 = L.xy[idx];
+                const double2 q1 = L.zvx[idx];
+                const double ex = x[0] - q0.x, ey = x[1] - q0.y, ez = x[2] - q1.x;
+                const double sep2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                if (hill_close(sep2, mi, L.m[idx], inv24m0, rb, L.red[idx]))
+                    fl |= 2;
+            }
+        }
+    }
+    wave_sync();
+    return sys_or<N>(L, lane, s, fl);
+}
+
+// Integrate one tile (floor(64/N) systems) with one body per lane for at
+// most P.quantum steps.  Every lane of the wavefront executes the same
+// control flow (the LDS exchanges need it); lanes of finished, padding or
+// absent systems compute but never commit.  Returns, on the star lane of each
+// present system, whether that system is still active.
+template <int N, bool ADV>
+__device__ bool bpl_run(const Bucket &B, const int first, const int count, const int *list,
+                        const StepParams &P, int &slot_out)
+{
+    constexpr int S = 64 / N;
+    BplLds &L = wave_lds();
+    const int lane = threadIdx.x & 63;
+    const int braw = lane / S;
+    const int b = braw < N ? braw : N - 1;
+    const int s = lane - braw * S;
+    const bool valid = braw < N && s < count;
+    int slot = 0;
+    if (valid)
+        slot = list ? list[first + s] : first + s;
+    slot_out = slot;
+    const size_t pitch = B.pitch;
+    double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
+    Clock c;
+    c.status = ST_DONE;
+    if (valid) {
+        mi = B.st[(R_M * N + b) * pitch + slot];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            x[cc] = B.st[((R_X + cc) * N + b) * pitch + slot];
+            v[cc] = B.st[((R_V + cc) * N + b) * pitch + slot];
+            a0[cc] = B.st[((R_A + cc) * N + b) * pitch + slot];
+            j0[cc] = B.st[((R_J + cc) * N + b) * pitch + slot];
+        }
+        c = load_clock(B, slot);
+    }
+    L.m[lane] = mi;
+    wave_sync();
+    for (int q = 0; q < P.quantum; ++q) {
+        double h = 0.0;
+        bool last = false;
+        const bool act = valid && plan_step(c, P, h, last);
+        if (!__any(act))
+            break;
+        const Coef k = make_coef(h);
+        double xc[3], vc[3], bx[3], bv[3], ak[3], jk[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            predict_comp(k, x[cc], v[cc], a0[cc], j0[cc], xc[cc], vc[cc], bx[cc], bv[cc]);
+        double w = 0.0;
+        bpl_eval<N, false>(L, lane, b, s, xc, vc, ak, jk, w);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
+        bpl_eval<N, ADV>(L, lane, b, s, xc, vc, ak, jk, w);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
+        double dtp = 0.0;
+        if (ADV && P.adaptive)
+            dtp = P.eta * rsqrt_nr(sys_max<N>(L, lane, s, w));
+        if (act) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                x[cc] = xc[cc];
+                v[cc] = vc[cc];
+                a0[cc] = ak[cc];
+                j0[cc] = jk[cc];
+            }
+            finish_step(c, P, last, h, dtp);
+        }
+        if (ADV) {
+            const int fl = bpl_stop_flags<N>(L, lane, b, s, mi, x, v, P);
+            if (act && fl)
+                c.status = status_of_flags(fl);
+        }
+    }
+    if (!ADV) {
+        const int fl = sys_or<N>(L, lane, s, (finite3(x) && finite3(v)) ? 0 : 1);
+        if (valid && fl)
+            c.status = ST_NONFINITE;
+    }
+    if (valid) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            B.st[((R_X + cc) * N + b) * pitch + slot] = x[cc];
+            B.st[((R_V + cc) * N + b) * pitch + slot] = v[cc];
+            B.st[((R_A + cc) * N + b) * pitch + slot] = a0[cc];
+            B.st[((R_J + cc) * N + b) * pitch + slot] = j0[cc];
+        }
+        if (b == 0)
+            store_clock(B, slot, c);
+    }
+    return valid && b == 0 && braw == 0 && c.status == ST_ACTIVE;
+}
+
+// ---------------------------------------------------------------------------
+// kernels: plain schedule (one launch per homogeneous bucket)
+// ---------------------------------------------------------------------------
+template <int N, bool ADV>
+__global__ __launch_bounds__(256) void k_plain_spl(Bucket B, StepParams P)
+{
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot < B.count)
+        spl_run<N, ADV>(B, slot, P);
+}
+
+template <int N, bool ADV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FB_BPL_WAVES)))
+void k_plain_bpl(Bucket B, StepParams P)
+{
+    constexpr int S = 64 / N;
+    const int wave = threadIdx.x >> 6;
+    const int tile = blockIdx.x * (blockDim.x >> 6) + wave;
+    const int first = tile * S;
+    if (first >= B.count)
+        return;
+    const int count = min(S, B.count - first);
+    int slot;
+    bpl_run<N, ADV>(B, first, count, nullptr, P, slot);
+}
+
+// ---------------------------------------------------------------------------
+// kernel: persistent schedule (one fused launch over every bucket)
+// ---------------------------------------------------------------------------
+
+// Append the systems flagged by `keep` to bucket `bk`'s survivor list
+// (wave-aggregated: one atomic per wavefront).
+__device__ __forceinline__ void append_survivors(const ActiveLists &AL, int bk, bool keep,
+                                                 int slot)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(keep);
+    if (mask == 0ull)
+        return;
+    const int cnt = __popcll(mask);
+    int base = 0;
+    if (lane == 0)
+        base = atomicAdd(&AL.next_count[bk], cnt);
+    base = __builtin_amdgcn_readfirstlane(base);
+    const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+    if (keep)
+        AL.next[AL.base[bk] + base + pre] = slot;
+}
+
+template <int N, bool ADV>
+__device__ __noinline__ bool spl_tile(const Bucket &B, const Tile &T, const int *list,
+                                      const StepParams &P, int &slot)
+{
+    const int lane = threadIdx.x & 63;
+    slot = 0;
+    if (lane >= T.count)
+        return false;
+    slot = list ? list[T.first + lane] : T.first + lane;
+    spl_run<N, ADV>(B, slot, P);
+    return B.status[slot] == ST_ACTIVE;
+}
+
+template <int N, bool ADV>
+__device__ __noinline__ bool bpl_tile(const Bucket &B, const Tile &T, const int *list,
+                                      const StepParams &P, int &slot)
+{
+    return bpl_run<N, ADV>(B, T.first, T.count, list, P, slot);
+}
+
+template <bool ADV>
+__device__ __forceinline__ bool run_tile(const Bucket &B, const Tile &T, const int *list,
+                                         const StepParams &P, int &slot)
+{
+    const int map = T.kind >> 5;
+    const int n = T.kind & 31;
+    if (map == MAP_SPL) {
+        switch (n) {
+        case 2: return spl_tile<2, ADV>(B, T, list, P, slot);
+        case 3: return spl_tile<3, ADV>(B, T, list, P, slot);
+        default: break;
+        }
+    }
+    switch (n) {
+#define FB_BPL_CASE(NN) case NN: return bpl_tile<NN, ADV>(B, T, list, P, slot);
+        FB_BPL_CASE(2) FB_BPL_CASE(3) FB_BPL_CASE(4) FB_BPL_CASE(5) FB_BPL_CASE(6)
+        FB_BPL_CASE(7) FB_BPL_CASE(8) FB_BPL_CASE(9) FB_BPL_CASE(10) FB_BPL_CASE(11)
+        FB_BPL_CASE(12) FB_BPL_CASE(13) FB_BPL_CASE(14) FB_BPL_CASE(15) FB_BPL_CASE(16)
+#undef FB_BPL_CASE
+    default: return false;
+    }
+}
+
+template <bool ADV, bool COMPACT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FB_BPL_WAVES)))
+void k_persistent(const Bucket *__restrict__ buckets, const Tile *__restrict__ tiles,
+                  const int *__restrict__ ntiles_p, int *__restrict__ head, const int *lists,
+                  StepParams P, ActiveLists AL)
+{
+    const int ntiles = *ntiles_p;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int t = 0;
+        if (lane == 0)
+            t = atomicAdd(head, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntiles)
+            break;
+        const Tile T = tiles[t];
+        const Bucket B = buckets[T.bucket];
+        int slot = 0;
+        const bool keep = run_tile<ADV>(B, T, lists, P, slot);
+        if (COMPACT)
+            append_survivors(AL, T.bucket, keep, slot);
+    }
+}
+
+// Tiles for the next quantum from the survivor counts (one workgroup):
+// buckets in the given order (longest work first), tiles of each bucket in
+// list order; resets the queue head and the other list's counts.
+__global__ void k_build_tiles(const Bucket *__restrict__ buckets, int nb,
+                              const int *__restrict__ order, const int *__restrict__ mapping,
+                              ActiveLists AL, Tile *__restrict__ tiles, int *ntiles,
+                              int *head)
+{
+    __shared__ int start[kMaxBodies + 2];
+    __shared__ int cap[kMaxBodies + 2];
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < nb; ++i) {
+            const int bk = order[i];
+            const int n = buckets[bk].n;
+            const int c = (mapping[bk] == MAP_SPL) ? 64 : 64 / n;
+            cap[i] = c;
+            start[i] = acc;
+            acc += (AL.cur_count[bk] + c - 1) / c;
+        }
+        start[nb] = acc;
+        *ntiles = acc;
+        *head = 0;
+    }
+    __syncthreads();
+    for (int i = 0; i < nb; ++i) {
+        const int bk = order[i];
+        const int n = buckets[bk].n;
+        const int cnt = AL.cur_count[bk];
+        const int c = cap[i];
+        for (int t = threadIdx.x; t < start[i + 1] - start[i]; t += blockDim.x) {
+            Tile T;
+            T.bucket = bk;
+            T.first = AL.base[bk] + t * c;
+            T.count = min(c, cnt - t * c);
+            T.kind = mapping[bk] * 32 + n;
+            tiles[start[i] + t] = T;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        AL.next_count[i] = 0;
+}
+
+__global__ void k_fill_int(int *p, int n, int value)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// set-up, run control, layout and diagnostics kernels (one thread per slot)
+// ---------------------------------------------------------------------------
+
+// AoS (caller order) -> bucket SoA; validates the inputs.
+__global__ void k_pack(Bucket B, const double *__restrict__ mass, const double *__restrict__ pos,
+                       const double *__restrict__ vel, const double *__restrict__ t0,
+                       const long long *__restrict__ orig_off, int *bad)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.pitch)
+        return;
+    const size_t pitch = B.pitch;
+    const int n = B.n;
+    if (s >= B.count) {   // padding slots: inert, finished
+        B.status[s] = ST_DONE;
+        B.t[s] = 0.0;
+        B.steps[s] = 0;
+        return;
+    }
+    const int o = B.orig[s];
+    const long long base = orig_off[o];
+    bool ok = true;
+    for (int b = 0; b < n; ++b) {
+        const double m = mass[base + b];
+        ok = ok && __builtin_isfinite(m) && m >= 0.0;
+        B.st[(R_M * n + b) * pitch + s] = m;
+        for (int c = 0; c < 3; ++c) {
+            const double xv = pos[3 * (base + b) + c];
+            const double vv = vel[3 * (base + b) + c];
+            ok = ok && __builtin_isfinite(xv) && __builtin_isfinite(vv);
+            B.st[((R_X + c) * n + b) * pitch + s] = xv;
+            B.st[((R_V + c) * n + b) * pitch + s] = vv;
+        }
+    }
+    const double tt = t0 ? t0[o] : 0.0;
+    ok = ok && __builtin_isfinite(tt);
+    B.t[s] = tt;
+    B.t0run[s] = tt;
+    B.t_end[s] = tt;
+    B.dt[s] = 0.0;
+    B.dtn[s] = 0.0;
+    B.krun[s] = 0;
+    B.nfull[s] = 0;
+    B.steps[s] = 0;
+    B.status[s] = ST_DONE;
+    if (!ok)
+        atomicOr(bad, 1);
+}
+
+template <int N>
+__device__ __forceinline__ void load_xv(const Bucket &B, int s, double (&m)[N], double (&x)[N][3],
+                                        double (&v)[N][3])
+{
+    const size_t pitch = B.pitch;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        m[b] = B.st[(R_M * N + b) * pitch + s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[b][c] = B.st[((R_X + c) * N + b) * pitch + s];
+            v[b][c] = B.st[((R_V + c) * N + b) * pitch + s];
+        }
+    }
+}
+
+// Algorithm 1's "prepare": (a0, j0) at the initial state.
+template <int N>
+__global__ void k_prepare(Bucket B)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3], a[N][3], jk[N][3];
+    load_xv<N>(B, s, m, x, v);
+    double w = 0.0;
+    spl_accjerk<N, false>(m, x, v, a, jk, w);
+    const size_t pitch = B.pitch;
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            B.st[((R_A + c) * N + b) * pitch + s] = a[b][c];
+            B.st[((R_J + c) * N + b) * pitch + s] = jk[b][c];
+        }
+}
+
+// Start a run.  fixed_steps: exactly n_steps steps of dt.  Otherwise to
+// t_end, with fixed dt or (adaptive) the carried step, proposing one from
+// the current state when none is carried yet.  Systems stopped by a rule
+// keep their status.
+template <int N>
+__global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double t_end,
+                            double dt, int adaptive, double eta)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    const int st = B.status[s];
+    if (st != ST_ACTIVE && st != ST_DONE && st != ST_MAXSTEPS)
+        return;
+    const double t = B.t[s];
+    B.t0run[s] = t;
+    B.krun[s] = 0;
+    if (fixed_steps) {
+        B.dt[s] = dt;
+        B.nfull[s] = n_steps;
+        B.t_end[s] = fma((double)n_steps, dt, t);
+        B.status[s] = n_steps > 0 ? ST_ACTIVE : ST_DONE;
+        return;
+    }
+    B.t_end[s] = t_end;
+    if (adaptive) {
+        B.nfull[s] = 0;
+        B.dt[s] = 0.0;
+        B.status[s] = t < t_end ? ST_ACTIVE : ST_DONE;
+        if (!(B.dtn[s] > 0.0)) {
+            double m[N], x[N][3], v[N][3], a[N][3], jk[N][3];
+            load_xv<N>(B, s, m, x, v);
+            double w = 0.0;
+            spl_accjerk<N, true>(m, x, v, a, jk, w);
+            B.dtn[s] = eta * rsqrt_nr(w);
+        }
+        return;
+    }
+    B.dt[s] = dt;
+    const double span = (t_end - t) / dt;
+    long long nf = span > 0.0 ? (long long)floor(span) : 0;
+    while (nf > 0 && (fma((double)nf, dt, t) - t_end) * dt > 0.0)
+        --nf;
+    B.nfull[s] = nf;
+    B.status[s] = (t_end - t) * dt > 0.0 ? ST_ACTIVE : ST_DONE;
+}
+
+// bucket SoA -> AoS rows in caller order (any output may be null).
+__global__ void k_unpack(Bucket B, const long long *__restrict__ orig_off, double *pos,
+                         double *vel, double *acc, double *jerk, double *t, int *status,
+                         long long *steps, double *dtn)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    const size_t pitch = B.pitch;
+    const int n = B.n;
+    const int o = B.orig[s];
+    const long long base = orig_off[o];
+    for (int b = 0; b < n; ++b)
+        for (int c = 0; c < 3; ++c) {
+            const size_t row = 3 * (base + b) + c;
+            if (pos) pos[row] = B.st[((R_X + c) * n + b) * pitch + s];
+            if (vel) vel[row] = B.st[((R_V + c) * n + b) * pitch + s];
+            if (acc) acc[row] = B.st[((R_A + c) * n + b) * pitch + s];
+            if (jerk) jerk[row] = B.st[((R_J + c) * n + b) * pitch + s];
+        }
+    if (t) t[o] = B.t[s];
+    if (status) status[o] = B.status[s];
+    if (steps) steps[o] = B.steps[s];
+    if (dtn) dtn[o] = B.dtn[s];
+}
+
+// Energy (each pair once) and angular momentum about the origin.
+template <int N>
+__global__ void k_diag(Bucket B, double *energy, double *angmom)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3];
+    load_xv<N>(B, s, m, x, v);
+    double kin = 0.0, pot = 0.0, L0 = 0.0, L1 = 0.0, L2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        kin += 0.5 * m[i] * fma(v[i][2], v[i][2], fma(v[i][1], v[i][1], v[i][0] * v[i][0]));
+        L0 += m[i] * (x[i][1] * v[i][2] - x[i][2] * v[i][1]);
+        L1 += m[i] * (x[i][2] * v[i][0] - x[i][0] * v[i][2]);
+        L2 += m[i] * (x[i][0] * v[i][1] - x[i][1] * v[i][0]);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) {
+            const double dx = x[i][0] - x[j][0], dy = x[i][1] - x[j][1], dz = x[i][2] - x[j][2];
+            pot += m[i] * m[j] / sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+        }
+    const int o = B.orig[s];
+    if (energy)
+        energy[o] = kin - pot;
+    if (angmom) {
+        angmom[3 * o + 0] = L0;
+        angmom[3 * o + 1] = L1;
+        angmom[3 * o + 2] = L2;
+    }
+}
+
+__global__ void k_count_active(Bucket B, int *count)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = s < B.count && B.status[s] == ST_ACTIVE;
+    const unsigned long long mask = __ballot(act);
+    if ((threadIdx.x & 63) == 0 && mask)
+        atomicAdd(count, __popcll(mask));
+}
+
+inline dim3 grid_for(int n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define FB_SWITCH_N(n, MACRO)                                                           \
+    switch (n) {                                                                        \
+    case 2: MACRO(2); break;  case 3: MACRO(3); break;  case 4: MACRO(4); break;        \
+    case 5: MACRO(5); break;  case 6: MACRO(6); break;  case 7: MACRO(7); break;        \
+    case 8: MACRO(8); break;  case 9: MACRO(9); break;  case 10: MACRO(10); break;      \
+    case 11: MACRO(11); break; case 12: MACRO(12); break; case 13: MACRO(13); break;    \
+    case 14: MACRO(14); break; case 15: MACRO(15); break; case 16: MACRO(16); break;    \
+    default: return hipErrorInvalidValue;                                               \
+    }
+
+hipError_t launch_pack(const Bucket &B, const double *mass, const double *pos,
+                       const double *vel, const double *t0, const long long *orig_off, int *bad,
+                       hipStream_t s)
+{
+    if (B.pitch == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pack, grid_for(B.pitch, 256), dim3(256), 0, s, B, mass, pos, vel, t0,
+                       orig_off, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Bucket &B, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN) hipLaunchKernelGGL(k_prepare<NN>, grid_for(B.count, 64), dim3(64), 0, s, B)
+    FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_run(const Bucket &B, int fixed_steps, long long n_steps, double t_end,
+                            double dt, int adaptive, double eta, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN)                                                                        \
+    hipLaunchKernelGGL(k_begin_run<NN>, grid_for(B.count, 64), dim3(64), 0, s, B,       \
+                       fixed_steps, n_steps, t_end, dt, adaptive, eta)
+    FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const StepParams &P,
+                        hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+    const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
+    const bool adv = P.adaptive || P.stop_rules;
+    if (mapping == MAP_SPL && B.n <= kMaxSplBodies) {
+        const dim3 grid = grid_for(B.count, 64 * W);
+#define FB_L(NN)                                                                        \
+    if (adv) hipLaunchKernelGGL((k_plain_spl<NN, true>), grid, dim3(64 * W), 0, s, B, P);  \
+    else hipLaunchKernelGGL((k_plain_spl<NN, false>), grid, dim3(64 * W), 0, s, B, P)
+        switch (B.n) {
+        case 2: FB_L(2); break;
+        case 3: FB_L(3); break;
+        case 4: FB_L(4); break;
+        case 5: FB_L(5); break;
+        case 6: FB_L(6); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef FB_L
+        return hipGetLastError();
+    }
+    const int S = 64 / B.n;
+    const int tiles = (B.count + S - 1) / S;
+    const dim3 grid((unsigned)((tiles + W - 1) / W));
+    const size_t lds = sizeof(BplLds) * W;
+#define FB_L(NN)                                                                           \
+    if (adv) hipLaunchKernelGGL((k_plain_bpl<NN, true>), grid, dim3(64 * W), lds, s, B, P);  \
+    else hipLaunchKernelGGL((k_plain_bpl<NN, false>), grid, dim3(64 * W), lds, s, B, P)
+    FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+size_t persistent_lds_bytes(int waves_per_group) { return sizeof(BplLds) * waves_per_group; }
+
+int persistent_max_groups_per_cu(int adv, int waves_per_group)
+{
+    int blocks = 0;
+    const int threads = 64 * waves_per_group;
+    const size_t lds = persistent_lds_bytes(waves_per_group);
+    hipError_t e;
+    if (adv)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<true, true>,
+                                                         threads, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<false, false>,
+                                                         threads, lds);
+    return e == hipSuccess ? blocks : 0;
+}
+
+hipError_t launch_persistent(const Bucket *d_buckets, const Tile *d_tiles, const int *d_ntiles,
+                             int *d_head, const int *d_lists, const StepParams &P, int adv,
+                             int grid, int waves_per_group, ActiveLists *compact, hipStream_t s)
+{
+    const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
+    const size_t lds = persistent_lds_bytes(W);
+    ActiveLists AL = compact ? *compact : ActiveLists{nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (adv) {
+        if (compact)
+            hipLaunchKernelGGL((k_persistent<true, true>), dim3(grid), dim3(64 * W), lds, s,
+                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
+        else
+            hipLaunchKernelGGL((k_persistent<true, false>), dim3(grid), dim3(64 * W), lds, s,
+                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
+    } else {
+        if (compact)
+            hipLaunchKernelGGL((k_persistent<false, true>), dim3(grid), dim3(64 * W), lds, s,
+                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
+        else
+            hipLaunchKernelGGL((k_persistent<false, false>), dim3(grid), dim3(64 * W), lds, s,
+                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_build_tiles(const Bucket *d_buckets, int n_buckets, const int *d_order,
+                              const int *d_mapping, ActiveLists L, Tile *d_tiles, int *d_ntiles,
+                              int *d_head, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_build_tiles, dim3(1), dim3(256), 0, s, d_buckets, n_buckets, d_order,
+                       d_mapping, L, d_tiles, d_ntiles, d_head);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(int *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_int, grid_for(n, 256), dim3(256), 0, s, p, n, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos, double *vel,
+                         double *acc, double *jerk, double *t, int *status, long long *steps,
+                         double *dt_next, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_unpack, grid_for(B.count, 256), dim3(256), 0, s, B, orig_off, pos, vel,
+                       acc, jerk, t, status, steps, dt_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN) hipLaunchKernelGGL(k_diag<NN>, grid_for(B.count, 64), dim3(64), 0, s, B, energy, angmom)
+    FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_count_active, grid_for(B.count, 256), dim3(256), 0, s, B, count);
+    return hipGetLastError();
+}
+
+}  // namespace fb

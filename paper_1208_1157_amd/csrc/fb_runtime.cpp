@@ -1,0 +1,931 @@
+// fb_runtime.cpp -- host runtime behind include/fewbody.h.
+//
+// An ensemble is laid out in device memory as one structure-of-arrays
+// bucket per body count (systems of equal n side by side, slot fastest), so
+// every launch is homogeneous in n and every load is coalesced.  The
+// runtime owns the layout, the per-n launch plans, the plain (one launch per
+// bucket) and persistent (one fused launch over a tile queue, optionally
+// replayed as a captured HIP graph per quantum, with compaction of retired
+// systems) schedules, and the HIP-event kernel timer.
+#include "fewbody.h"
+#include "fb_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace fb;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_err;
+
+fb_status fail(fb_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+fb_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? FB_E_NOMEM : FB_E_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define FB_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess)                         \
+            return hip_fail(e_, #call);               \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+struct Plan {
+    int mapping;          // MAP_SPL / MAP_BPL
+    int waves_per_group;  // 1..4
+    int groups_per_cu;    // persistent schedule only (entry 0)
+};
+
+std::mutex g_plan_mu;
+Plan g_plan[kMaxBodies + 1];
+bool g_plan_init = false;
+
+void init_plans_locked()
+{
+    if (g_plan_init)
+        return;
+    for (int n = 0; n <= kMaxBodies; ++n)
+        g_plan[n] = Plan{n <= 3 ? MAP_SPL : MAP_BPL, n <= 3 ? 4 : 2, 0};
+    g_plan[0] = Plan{MAP_BPL, 2, 8};
+    g_plan_init = true;
+}
+
+Plan get_plan(int n)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    init_plans_locked();
+    Plan p = g_plan[n];
+    if (n > 0 && p.mapping == MAP_SPL && n > kMaxSplBodies)
+        p.mapping = MAP_BPL;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timer (HIP events on the launch stream)
+// ---------------------------------------------------------------------------
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+double g_prof_ms = 0.0;
+int64_t g_prof_launches = 0;
+
+struct ProfScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit ProfScope(hipStream_t st) : s(st)
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on)
+            return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!a)
+            return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_events.emplace_back(a, b);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// layout
+// ---------------------------------------------------------------------------
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct BucketLayout {
+    int n, count, pitch;
+    size_t st, t, t_end, dt, dtn, t0run, krun, nfull, steps, status, orig;   // byte offsets
+};
+
+struct Layout {
+    std::vector<BucketLayout> b;
+    int64_t n_bodies = 0;
+    int max_tiles = 0;
+    int list_total = 0;
+    size_t buckets, orig_off, staging, diag, ints, tiles, lists0, lists1, list_base, counts0,
+        counts1, order, mapping, total;
+};
+
+// Returns false for an invalid shape.
+bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L)
+{
+    if (n_sys < 0 || (n_sys > 0 && !n_body))
+        return false;
+    int cnt[kMaxBodies + 1] = {0};
+    int64_t nb = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        if (n_body[s] < 2 || n_body[s] > kMaxBodies)
+            return false;
+        cnt[n_body[s]]++;
+        nb += n_body[s];
+    }
+    L.n_bodies = nb;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.max_tiles = 0;
+    L.list_total = 0;
+    for (int n = kMaxBodies; n >= 2; --n) {   // buckets in descending n: longest work first
+        if (!cnt[n])
+            continue;
+        BucketLayout bl;
+        bl.n = n;
+        bl.count = cnt[n];
+        bl.pitch = (int)align_up((size_t)cnt[n], 64);
+        const size_t P = bl.pitch;
+        bl.st = take(sizeof(double) * R_COUNT * n * P);
+        bl.t = take(8 * P);
+        bl.t_end = take(8 * P);
+        bl.dt = take(8 * P);
+        bl.dtn = take(8 * P);
+        bl.t0run = take(8 * P);
+        bl.krun = take(8 * P);
+        bl.nfull = take(8 * P);
+        bl.steps = take(8 * P);
+        bl.status = take(4 * P);
+        bl.orig = take(4 * P);
+        L.max_tiles += (cnt[n] + (64 / n) - 1) / (64 / n);
+        L.list_total += bl.pitch;
+        L.b.push_back(bl);
+    }
+    const size_t nbk = L.b.size();
+    L.buckets = take(sizeof(Bucket) * std::max<size_t>(nbk, 1));
+    L.orig_off = take(8 * ((size_t)n_sys + 1));
+    L.staging = take(8 * (12 * (size_t)nb + 4 * (size_t)n_sys + 1));
+    L.diag = take(8 * 4 * ((size_t)n_sys + 1));
+    L.ints = take(4 * 64);
+    L.tiles = take(sizeof(Tile) * ((size_t)L.max_tiles + 1));
+    L.lists0 = take(4 * ((size_t)L.list_total + 1));
+    L.lists1 = take(4 * ((size_t)L.list_total + 1));
+    L.list_base = take(4 * (nbk + 1));
+    L.counts0 = take(4 * (nbk + 1));
+    L.counts1 = take(4 * (nbk + 1));
+    L.order = take(4 * (nbk + 1));
+    L.mapping = take(4 * (nbk + 1));
+    L.total = off;
+    return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ensemble object
+// ---------------------------------------------------------------------------
+struct fb_ensemble {
+    int device = 0;
+    int num_cu = 256;
+    hipStream_t stream = nullptr;
+    int32_t n_sys = 0;
+    std::vector<int32_t> n_body;
+    Layout L;
+    char *base = nullptr;
+    bool owns = false;
+    std::vector<Bucket> buckets;    // host copies of the device views
+    Bucket *d_buckets = nullptr;
+    long long *d_orig_off = nullptr;
+    double *d_staging = nullptr;
+    double *d_diag = nullptr;
+    int *d_ints = nullptr;          // [0] bad flag, [1] ntiles, [2] head, [3] active count
+    Tile *d_tiles = nullptr;
+    int *d_lists[2] = {nullptr, nullptr};
+    int *d_list_base = nullptr;
+    int *d_counts[2] = {nullptr, nullptr};
+    int *d_order = nullptr;
+    int *d_mapping = nullptr;
+    int *h_pinned = nullptr;        // pinned host ints for control reads
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+template <class T>
+T *at(fb_ensemble *e, size_t off)
+{
+    return reinterpret_cast<T *>(e->base + off);
+}
+
+fb_status bind_layout(fb_ensemble *e)
+{
+    e->buckets.clear();
+    for (const BucketLayout &bl : e->L.b) {
+        Bucket B;
+        B.st = at<double>(e, bl.st);
+        B.t = at<double>(e, bl.t);
+        B.t_end = at<double>(e, bl.t_end);
+        B.dt = at<double>(e, bl.dt);
+        B.dtn = at<double>(e, bl.dtn);
+        B.t0run = at<double>(e, bl.t0run);
+        B.krun = at<long long>(e, bl.krun);
+        B.nfull = at<long long>(e, bl.nfull);
+        B.steps = at<long long>(e, bl.steps);
+        B.status = at<int>(e, bl.status);
+        B.orig = at<int>(e, bl.orig);
+        B.n = bl.n;
+        B.pitch = bl.pitch;
+        B.count = bl.count;
+        B.pad = 0;
+        e->buckets.push_back(B);
+    }
+    e->d_buckets = at<Bucket>(e, e->L.buckets);
+    e->d_orig_off = at<long long>(e, e->L.orig_off);
+    e->d_staging = at<double>(e, e->L.staging);
+    e->d_diag = at<double>(e, e->L.diag);
+    e->d_ints = at<int>(e, e->L.ints);
+    e->d_tiles = at<Tile>(e, e->L.tiles);
+    e->d_lists[0] = at<int>(e, e->L.lists0);
+    e->d_lists[1] = at<int>(e, e->L.lists1);
+    e->d_list_base = at<int>(e, e->L.list_base);
+    e->d_counts[0] = at<int>(e, e->L.counts0);
+    e->d_counts[1] = at<int>(e, e->L.counts1);
+    e->d_order = at<int>(e, e->L.order);
+    e->d_mapping = at<int>(e, e->L.mapping);
+    return FB_OK;
+}
+
+// Upload the host-side tables (bucket views, slot -> caller index map, body
+// offsets, list bases) with synchronous copies; the staging of the inputs
+// must already be enqueued or resident.
+fb_status upload_tables(fb_ensemble *e)
+{
+    const int ns = e->n_sys;
+    std::vector<long long> off(ns + 1, 0);
+    for (int s = 0; s < ns; ++s)
+        off[s + 1] = off[s] + e->n_body[s];
+    std::vector<int> fill[kMaxBodies + 1];
+    for (int s = 0; s < ns; ++s)
+        fill[e->n_body[s]].push_back(s);
+    FB_HIP(hipMemcpyAsync(e->d_orig_off, off.data(), sizeof(long long) * (ns + 1),
+                          hipMemcpyHostToDevice, e->stream));
+    std::vector<int> list_base;
+    int acc = 0;
+    for (const Bucket &B : e->buckets) {
+        std::vector<int> &v = fill[B.n];
+        v.resize(B.pitch, 0);
+        FB_HIP(hipMemcpyAsync(B.orig, v.data(), sizeof(int) * B.pitch, hipMemcpyHostToDevice,
+                              e->stream));
+        list_base.push_back(acc);
+        acc += B.pitch;
+    }
+    const int nbk = (int)e->buckets.size();
+    if (nbk) {
+        FB_HIP(hipMemcpyAsync(e->d_buckets, e->buckets.data(), sizeof(Bucket) * nbk,
+                              hipMemcpyHostToDevice, e->stream));
+        FB_HIP(hipMemcpyAsync(e->d_list_base, list_base.data(), sizeof(int) * nbk,
+                              hipMemcpyHostToDevice, e->stream));
+        std::vector<int> order(nbk);
+        for (int i = 0; i < nbk; ++i)
+            order[i] = i;   // buckets are laid out in descending n already
+        FB_HIP(hipMemcpyAsync(e->d_order, order.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
+                              e->stream));
+    }
+    // the vectors above die at return: wait for the copies
+    FB_HIP(hipStreamSynchronize(e->stream));
+    return FB_OK;
+}
+
+fb_status finish_create(fb_ensemble *e, const double *d_mass, const double *d_pos,
+                        const double *d_vel, const double *d_t0)
+{
+    fb_status st = upload_tables(e);
+    if (st != FB_OK)
+        return st;
+    FB_HIP(launch_reset_counter(e->d_ints, 64, e->stream));
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_pack(B, d_mass, d_pos, d_vel, d_t0, e->d_orig_off, e->d_ints, e->stream));
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_prepare(B, e->stream));
+    FB_HIP(hipMemcpyAsync(e->h_pinned, e->d_ints, sizeof(int), hipMemcpyDeviceToHost, e->stream));
+    FB_HIP(hipStreamSynchronize(e->stream));
+    if (e->h_pinned[0])
+        return fail(FB_E_INVAL, "mass must be finite and >= 0; pos, vel and t0 finite");
+    return FB_OK;
+}
+
+fb_status alloc_common(fb_ensemble *e, void *hip_stream)
+{
+    e->stream = (hipStream_t)hip_stream;
+    FB_HIP(hipGetDevice(&e->device));
+    hipDeviceProp_t prop;
+    FB_HIP(hipGetDeviceProperties(&prop, e->device));
+    e->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    FB_HIP(hipHostMalloc((void **)&e->h_pinned, 64 * sizeof(int), hipHostMallocDefault));
+    return FB_OK;
+}
+
+void free_ensemble(fb_ensemble *e)
+{
+    if (!e)
+        return;
+    if (e->owns && e->base)
+        (void)hipFree(e->base);
+    if (e->h_pinned)
+        (void)hipHostFree(e->h_pinned);
+    if (e->capture_stream)
+        (void)hipStreamDestroy(e->capture_stream);
+    delete e;
+}
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i]))
+            return false;
+    return true;
+}
+
+StepParams make_params(const fb_opts &o, int quantum)
+{
+    StepParams P;
+    P.adaptive = o.adaptive ? 1 : 0;
+    P.stop_rules = o.stop_rules & (FB_STOP_ENCOUNTER | FB_STOP_EJECT);
+    P.eta = o.eta;
+    P.r_eject = o.r_eject;
+    P.max_steps = o.max_steps > 0 ? (long long)o.max_steps : LLONG_MAX;
+    P.quantum = quantum;
+    P.pad = 0;
+    return P;
+}
+
+fb_status check_opts(const fb_opts &o)
+{
+    if (o.adaptive && !(std::isfinite(o.eta) && o.eta > 0.0))
+        return fail(FB_E_INVAL, "eta must be finite and > 0");
+    if ((o.stop_rules & FB_STOP_EJECT) && !(o.r_eject > 0.0))
+        return fail(FB_E_INVAL, "r_eject must be > 0");
+    if (o.schedule != FB_SCHED_PLAIN && o.schedule != FB_SCHED_PERSISTENT)
+        return fail(FB_E_INVAL, "unknown schedule %d", o.schedule);
+    return FB_OK;
+}
+
+// Number of systems still ACTIVE (synchronises the stream).
+fb_status count_active(fb_ensemble *e, int &out)
+{
+    FB_HIP(launch_reset_counter(e->d_ints + 3, 1, e->stream));
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_count_active(B, e->d_ints + 3, e->stream));
+    FB_HIP(hipMemcpyAsync(e->h_pinned + 3, e->d_ints + 3, sizeof(int), hipMemcpyDeviceToHost,
+                          e->stream));
+    FB_HIP(hipStreamSynchronize(e->stream));
+    out = e->h_pinned[3];
+    return FB_OK;
+}
+
+// Plain schedule: one launch per bucket (one per quantum if quanta are set).
+fb_status run_plain(fb_ensemble *e, const fb_opts &o, long long step_bound)
+{
+    const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
+    for (;;) {
+        for (const Bucket &B : e->buckets) {
+            const Plan p = get_plan(B.n);
+            const StepParams P = make_params(o, quantum);
+            ProfScope ps(e->stream);
+            FB_HIP(launch_plain(B, p.mapping, p.waves_per_group, P, e->stream));
+        }
+        if (quantum == INT_MAX)
+            return FB_OK;
+        if (step_bound >= 0) {
+            step_bound -= quantum;
+            if (step_bound <= 0)
+                return FB_OK;
+            continue;
+        }
+        int act = 0;
+        fb_status st = count_active(e, act);
+        if (st != FB_OK)
+            return st;
+        if (act == 0)
+            return FB_OK;
+    }
+}
+
+// Persistent schedule: one fused launch per quantum over a tile queue; the
+// tiles cover every bucket, largest n first.  With compaction the tiles of
+// each quantum are rebuilt on the device from the previous quantum's
+// survivors.  Quanta are captured once into a HIP graph (two quanta, so the
+// survivor lists alternate) and replayed.
+fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
+{
+    const int nbk = (int)e->buckets.size();
+    if (nbk == 0)
+        return FB_OK;
+    const Plan p0 = get_plan(0);
+    const int W = std::max(1, std::min(4, p0.waves_per_group));
+    const bool adv = o.adaptive || o.stop_rules;
+    const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
+    int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
+    const int occ = persistent_max_groups_per_cu(adv ? 1 : 0, W);
+    if (occ > 0)
+        gpc = std::min(gpc, occ);
+    const int grid = std::max(1, gpc * e->num_cu);
+    const StepParams P = make_params(o, quantum);
+
+    // mapping per bucket, initial lists (identity) and counts
+    std::vector<int> mapping(nbk), counts(nbk), ident;
+    for (int i = 0; i < nbk; ++i) {
+        const int n = e->buckets[i].n;
+        const int m = get_plan(n).mapping;
+        mapping[i] = (m == MAP_SPL && n <= kMaxSplPersistent) ? MAP_SPL : MAP_BPL;
+        counts[i] = e->buckets[i].count;
+    }
+    ident.reserve(e->L.list_total);
+    for (const Bucket &B : e->buckets)
+        for (int s = 0; s < B.pitch; ++s)
+            ident.push_back(s);
+    FB_HIP(hipMemcpyAsync(e->d_mapping, mapping.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
+                          e->stream));
+    FB_HIP(hipMemcpyAsync(e->d_lists[0], ident.data(), sizeof(int) * ident.size(),
+                          hipMemcpyHostToDevice, e->stream));
+    FB_HIP(hipMemcpyAsync(e->d_counts[0], counts.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
+                          e->stream));
+    FB_HIP(hipStreamSynchronize(e->stream));   // host vectors die at return
+
+    ActiveLists AL[2];
+    for (int k = 0; k < 2; ++k) {
+        AL[k].cur = e->d_lists[k];
+        AL[k].next = e->d_lists[1 - k];
+        AL[k].base = e->d_list_base;
+        AL[k].cur_count = e->d_counts[k];
+        AL[k].next_count = e->d_counts[1 - k];
+    }
+    int *d_ntiles = e->d_ints + 1, *d_head = e->d_ints + 2;
+
+    const bool compact = o.compact != 0;
+    // Enqueue one quantum.  With compaction it reads lists/counts [k] and
+    // writes the survivors to [1-k]; without, every quantum re-runs the
+    // identity lists [0] (retired systems exit at once).
+    auto quantum_launch = [&](hipStream_t s, int k) -> hipError_t {
+        if (!compact)
+            k = 0;
+        hipError_t err = launch_build_tiles(e->d_buckets, nbk, e->d_order, e->d_mapping, AL[k],
+                                            e->d_tiles, d_ntiles, d_head, s);
+        if (err != hipSuccess)
+            return err;
+        ActiveLists al = AL[k];
+        return launch_persistent(e->d_buckets, e->d_tiles, d_ntiles, d_head, e->d_lists[k], P,
+                                 adv ? 1 : 0, grid, W, compact ? &al : nullptr, s);
+    };
+
+    if (quantum == INT_MAX) {
+        ProfScope ps(e->stream);
+        FB_HIP(quantum_launch(e->stream, 0));
+        return FB_OK;
+    }
+
+    // capture two quanta (0 -> 1 -> 0) into a graph
+    if (!e->capture_stream)
+        FB_HIP(hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    FB_HIP(hipStreamBeginCapture(e->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t cerr = quantum_launch(e->capture_stream, 0);
+    if (cerr == hipSuccess)
+        cerr = quantum_launch(e->capture_stream, 1);
+    hipError_t eerr = hipStreamEndCapture(e->capture_stream, &graph);
+    if (cerr != hipSuccess)
+        return hip_fail(cerr, "quantum capture");
+    FB_HIP(eerr);
+    hipError_t ierr = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ierr != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(ierr, "hipGraphInstantiate");
+    }
+    fb_status result = FB_OK;
+    long long done_steps = 0;
+    for (;;) {
+        {
+            ProfScope ps(e->stream);
+            hipError_t err = hipGraphLaunch(exec, e->stream);
+            if (err != hipSuccess) {
+                result = hip_fail(err, "hipGraphLaunch");
+                break;
+            }
+        }
+        done_steps += 2LL * quantum;
+        if (step_bound >= 0) {
+            if (done_steps >= step_bound)
+                break;
+            continue;
+        }
+        long long act = 0;
+        if (compact) {
+            // survivors of the second quantum sit in counts[0]
+            hipError_t err = hipMemcpyAsync(e->h_pinned + 8, e->d_counts[0], sizeof(int) * nbk,
+                                            hipMemcpyDeviceToHost, e->stream);
+            if (err == hipSuccess)
+                err = hipStreamSynchronize(e->stream);
+            if (err != hipSuccess) {
+                result = hip_fail(err, "active count");
+                break;
+            }
+            for (int i = 0; i < nbk; ++i)
+                act += e->h_pinned[8 + i];
+        } else {
+            int a = 0;
+            result = count_active(e, a);
+            if (result != FB_OK)
+                break;
+            act = a;
+        }
+        if (act == 0)
+            break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return result;
+}
+
+fb_status run(fb_ensemble *e, const fb_opts &o, long long step_bound)
+{
+    if (o.schedule == FB_SCHED_PERSISTENT)
+        return run_persistent(e, o, step_bound);
+    return run_plain(e, o, step_bound);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void fb_opts_default(fb_opts *o)
+{
+    if (!o)
+        return;
+    std::memset(o, 0, sizeof *o);
+    o->adaptive = 0;
+    o->eta = 0.01;
+    o->stop_rules = 0;
+    o->r_eject = 100.0;
+    o->max_steps = 0;
+    o->schedule = FB_SCHED_PLAIN;
+    o->steps_per_quantum = 0;
+    o->compact = 0;
+}
+
+size_t fb_workspace_bytes(int32_t n_sys, const int32_t *n_body)
+{
+    Layout L;
+    if (!make_layout(n_sys, n_body, L))
+        return 0;
+    return L.total;
+}
+
+fb_status fb_ensemble_create(int32_t n_sys, const int32_t *n_body, const double *mass,
+                             const double *pos, const double *vel, const double *t0,
+                             void *hip_stream, fb_ensemble **out)
+{
+    if (!out)
+        return fail(FB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    if (!make_layout(n_sys, n_body, L))
+        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxBodies);
+    const size_t N = (size_t)L.n_bodies;
+    if (N && (!mass || !pos || !vel))
+        return fail(FB_E_INVAL, "mass, pos and vel are required");
+    for (size_t i = 0; i < N; ++i)
+        if (!(std::isfinite(mass[i]) && mass[i] >= 0.0))
+            return fail(FB_E_INVAL, "mass[%zu] must be finite and >= 0", i);
+    if (!finite_all(pos, 3 * N) || !finite_all(vel, 3 * N))
+        return fail(FB_E_INVAL, "pos and vel must be finite");
+    if (t0 && !finite_all(t0, (size_t)n_sys))
+        return fail(FB_E_INVAL, "t0 must be finite");
+    fb_ensemble *e = new fb_ensemble();
+    e->n_sys = n_sys;
+    e->n_body.assign(n_body, n_body + n_sys);
+    e->L = L;
+    fb_status st = alloc_common(e, hip_stream);
+    if (st != FB_OK) {
+        free_ensemble(e);
+        return st;
+    }
+    hipError_t err = hipMalloc((void **)&e->base, L.total);
+    if (err != hipSuccess) {
+        free_ensemble(e);
+        return hip_fail(err, "hipMalloc(ensemble)");
+    }
+    e->owns = true;
+    bind_layout(e);
+    // stage the inputs: mass | pos | vel | t0
+    double *d_mass = e->d_staging, *d_pos = d_mass + N, *d_vel = d_pos + 3 * N;
+    double *d_t0 = t0 ? d_vel + 3 * N : nullptr;
+    err = hipMemcpyAsync(d_mass, mass, 8 * N, hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(d_pos, pos, 24 * N, hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(d_vel, vel, 24 * N, hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess && t0)
+        err = hipMemcpyAsync(d_t0, t0, 8 * (size_t)n_sys, hipMemcpyHostToDevice, e->stream);
+    if (err != hipSuccess) {
+        free_ensemble(e);
+        return hip_fail(err, "input upload");
+    }
+    st = finish_create(e, d_mass, d_pos, d_vel, d_t0);
+    if (st != FB_OK) {
+        free_ensemble(e);
+        return st;
+    }
+    *out = e;
+    return FB_OK;
+}
+
+fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body, const double *d_mass,
+                                    const double *d_pos, const double *d_vel, const double *d_t0,
+                                    void *d_workspace, size_t ws_bytes, void *hip_stream,
+                                    fb_ensemble **out)
+{
+    if (!out)
+        return fail(FB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    if (!make_layout(n_sys, n_body, L))
+        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxBodies);
+    if (L.n_bodies && (!d_mass || !d_pos || !d_vel))
+        return fail(FB_E_INVAL, "d_mass, d_pos and d_vel are required");
+    if (!d_workspace || ws_bytes < L.total)
+        return fail(FB_E_NOMEM, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+    if (((uintptr_t)d_workspace) % 256)
+        return fail(FB_E_INVAL, "workspace must be 256-byte aligned");
+    fb_ensemble *e = new fb_ensemble();
+    e->n_sys = n_sys;
+    e->n_body.assign(n_body, n_body + n_sys);
+    e->L = L;
+    fb_status st = alloc_common(e, hip_stream);
+    if (st != FB_OK) {
+        free_ensemble(e);
+        return st;
+    }
+    e->base = (char *)d_workspace;
+    e->owns = false;
+    bind_layout(e);
+    st = finish_create(e, d_mass, d_pos, d_vel, d_t0);
+    if (st != FB_OK) {
+        free_ensemble(e);
+        return st;
+    }
+    *out = e;
+    return FB_OK;
+}
+
+fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *po)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    if (o.adaptive)
+        return fail(FB_E_INVAL, "fb_integrate_steps takes fixed steps (opts.adaptive must be 0)");
+    if (n_steps < 0)
+        return fail(FB_E_INVAL, "n_steps must be >= 0");
+    if (!(std::isfinite(dt) && dt != 0.0))
+        return fail(FB_E_INVAL, "dt must be finite and non-zero");
+    fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    if (n_steps == 0 || e->n_sys == 0)
+        return FB_OK;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_begin_run(B, 1, n_steps, 0.0, dt, 0, 0.0, e->stream));
+    return run(e, o, o.stop_rules ? -1 : n_steps);
+}
+
+fb_status fb_integrate(fb_ensemble *e, double t_end, double dt, const fb_opts *po)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    if (!std::isfinite(t_end))
+        return fail(FB_E_INVAL, "t_end must be finite");
+    if (!o.adaptive && !(std::isfinite(dt) && dt != 0.0))
+        return fail(FB_E_INVAL, "dt must be finite and non-zero");
+    if (e->n_sys == 0)
+        return FB_OK;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_begin_run(B, 0, 0, t_end, dt, o.adaptive ? 1 : 0, o.eta, e->stream));
+    return run(e, o, -1);
+}
+
+fb_status fb_synchronize(fb_ensemble *e)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    FB_HIP(hipStreamSynchronize(e->stream));
+    return FB_OK;
+}
+
+fb_status fb_get_state(fb_ensemble *e, double *pos, double *vel, double *t, int32_t *status,
+                       int64_t *steps)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    const size_t N = (size_t)e->L.n_bodies, ns = (size_t)e->n_sys;
+    if (ns == 0)
+        return FB_OK;
+    double *d_pos = e->d_staging, *d_vel = d_pos + 3 * N, *d_t = d_vel + 3 * N;
+    long long *d_steps = (long long *)(d_t + ns);
+    int *d_status = (int *)(d_steps + ns);
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_unpack(B, e->d_orig_off, pos ? d_pos : nullptr, vel ? d_vel : nullptr,
+                             nullptr, nullptr, t ? d_t : nullptr, status ? d_status : nullptr,
+                             steps ? d_steps : nullptr, nullptr, e->stream));
+    if (pos)
+        FB_HIP(hipMemcpyAsync(pos, d_pos, 24 * N, hipMemcpyDeviceToHost, e->stream));
+    if (vel)
+        FB_HIP(hipMemcpyAsync(vel, d_vel, 24 * N, hipMemcpyDeviceToHost, e->stream));
+    if (t)
+        FB_HIP(hipMemcpyAsync(t, d_t, 8 * ns, hipMemcpyDeviceToHost, e->stream));
+    if (steps)
+        FB_HIP(hipMemcpyAsync(steps, d_steps, 8 * ns, hipMemcpyDeviceToHost, e->stream));
+    if (status)
+        FB_HIP(hipMemcpyAsync(status, d_status, 4 * ns, hipMemcpyDeviceToHost, e->stream));
+    FB_HIP(hipStreamSynchronize(e->stream));
+    return FB_OK;
+}
+
+fb_status fb_get_hermite_state(fb_ensemble *e, double *acc0, double *jerk0, double *dt_next)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    const size_t N = (size_t)e->L.n_bodies, ns = (size_t)e->n_sys;
+    if (ns == 0)
+        return FB_OK;
+    double *d_acc = e->d_staging, *d_jerk = d_acc + 3 * N, *d_dtn = d_jerk + 3 * N;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_unpack(B, e->d_orig_off, nullptr, nullptr, acc0 ? d_acc : nullptr,
+                             jerk0 ? d_jerk : nullptr, nullptr, nullptr, nullptr,
+                             dt_next ? d_dtn : nullptr, e->stream));
+    if (acc0)
+        FB_HIP(hipMemcpyAsync(acc0, d_acc, 24 * N, hipMemcpyDeviceToHost, e->stream));
+    if (jerk0)
+        FB_HIP(hipMemcpyAsync(jerk0, d_jerk, 24 * N, hipMemcpyDeviceToHost, e->stream));
+    if (dt_next)
+        FB_HIP(hipMemcpyAsync(dt_next, d_dtn, 8 * ns, hipMemcpyDeviceToHost, e->stream));
+    FB_HIP(hipStreamSynchronize(e->stream));
+    return FB_OK;
+}
+
+fb_status fb_diagnostics(fb_ensemble *e, double *energy, double *angmom)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    const size_t ns = (size_t)e->n_sys;
+    if (ns == 0)
+        return FB_OK;
+    double *d_E = e->d_diag, *d_L = d_E + ns;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_diag(B, d_E, d_L, e->stream));
+    if (energy)
+        FB_HIP(hipMemcpyAsync(energy, d_E, 8 * ns, hipMemcpyDeviceToHost, e->stream));
+    if (angmom)
+        FB_HIP(hipMemcpyAsync(angmom, d_L, 24 * ns, hipMemcpyDeviceToHost, e->stream));
+    FB_HIP(hipStreamSynchronize(e->stream));
+    return FB_OK;
+}
+
+fb_status fb_ensemble_shape(const fb_ensemble *e, int32_t *n_sys, int64_t *n_bodies)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    if (n_sys)
+        *n_sys = e->n_sys;
+    if (n_bodies)
+        *n_bodies = e->L.n_bodies;
+    return FB_OK;
+}
+
+fb_status fb_ensemble_destroy(fb_ensemble *e)
+{
+    if (!e)
+        return FB_OK;
+    (void)hipStreamSynchronize(e->stream);
+    free_ensemble(e);
+    return FB_OK;
+}
+
+fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group, int32_t groups_per_cu)
+{
+    if (n < 0 || n > kMaxBodies || n == 1)
+        return fail(FB_E_INVAL, "plan index must be 0 (persistent launch) or 2..%d", kMaxBodies);
+    if (mapping != FB_MAP_AUTO && mapping != FB_MAP_SYSTEM_PER_LANE &&
+        mapping != FB_MAP_BODY_PER_LANE)
+        return fail(FB_E_INVAL, "unknown mapping %d", mapping);
+    if (waves_per_group < 1 || waves_per_group > 4)
+        return fail(FB_E_INVAL, "waves_per_group must be 1..4");
+    if (groups_per_cu < 0 || groups_per_cu > 32)
+        return fail(FB_E_INVAL, "groups_per_cu must be 0..32");
+    if (mapping == FB_MAP_SYSTEM_PER_LANE && n > kMaxSplBodies)
+        return fail(FB_E_INVAL, "system-per-lane is built for n <= %d", kMaxSplBodies);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    init_plans_locked();
+    Plan &p = g_plan[n];
+    if (mapping != FB_MAP_AUTO)
+        p.mapping = mapping == FB_MAP_SYSTEM_PER_LANE ? MAP_SPL : MAP_BPL;
+    p.waves_per_group = waves_per_group;
+    p.groups_per_cu = groups_per_cu;
+    return FB_OK;
+}
+
+fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
+                      int32_t *groups_per_cu)
+{
+    if (n < 0 || n > kMaxBodies || n == 1)
+        return fail(FB_E_INVAL, "plan index must be 0 or 2..%d", kMaxBodies);
+    const Plan p = get_plan(n);
+    if (mapping)
+        *mapping = p.mapping == MAP_SPL ? FB_MAP_SYSTEM_PER_LANE : FB_MAP_BODY_PER_LANE;
+    if (waves_per_group)
+        *waves_per_group = p.waves_per_group;
+    if (groups_per_cu)
+        *groups_per_cu = p.groups_per_cu;
+    return FB_OK;
+}
+
+fb_status fb_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return FB_OK;
+}
+
+fb_status fb_profile_read(double *kernel_ms, int64_t *launches)
+{
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        ev.swap(g_prof_events);
+    }
+    double ms = 0.0;
+    int64_t n = 0;
+    for (auto &p : ev) {
+        float f = 0.0f;
+        if (hipEventSynchronize(p.second) == hipSuccess &&
+            hipEventElapsedTime(&f, p.first, p.second) == hipSuccess) {
+            ms += f;
+            ++n;
+        }
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_ms += ms;
+    g_prof_launches += n;
+    if (kernel_ms)
+        *kernel_ms = g_prof_ms;
+    if (launches)
+        *launches = g_prof_launches;
+    g_prof_ms = 0.0;
+    g_prof_launches = 0;
+    return FB_OK;
+}
+
+const char *fb_last_error(void) { return g_err.c_str(); }
+
+const char *fb_version(void) { return "fewbody-hip 0.1 (gfx950, FP64 Hermite P(EC)^2)"; }
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+symbol the header declares, and rejects bad arguments with the documented
+codes before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fewbody.h")
+
+
+@pytest.fixture(scope="module")
+def fbmod():
+    from paper_1208_1157_amd import fewbody
+    return fewbody
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(fbmod):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(fbmod.lib(), n), f"{n} declared in fewbody.h but not exported"
+
+
+def test_opts_layout_and_defaults(fbmod):
+    o = fbmod.FbOpts()
+    fbmod.lib().fb_opts_default(ctypes.byref(o))
+    assert (o.adaptive, o.eta, o.stop_rules, o.r_eject, o.max_steps) == (0, 0.01, 0, 100.0, 0)
+    assert (o.schedule, o.steps_per_quantum, o.compact) == (0, 0, 0)
+    assert ctypes.sizeof(fbmod.FbOpts) == 56
+
+
+def test_version(fbmod):
+    assert "gfx950" in fbmod.version()
+
+
+def test_workspace_bytes(fbmod):
+    assert fbmod.workspace_bytes([3, 3, 5]) > 0
+    assert fbmod.workspace_bytes([]) > 0
+    assert fbmod.workspace_bytes([1]) == 0          # n_body below 2
+    assert fbmod.workspace_bytes([17]) == 0         # n_body above 16
+    a = fbmod.workspace_bytes([3] * 1000)
+    b = fbmod.workspace_bytes([3] * 2000)
+    assert b > a
+
+
+def _create(fbmod, n_body, mass, pos, vel):
+    h = ctypes.c_void_p()
+    nb = np.ascontiguousarray(n_body, dtype=np.int32)
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in (mass, pos, vel)]
+    rc = fbmod.lib().fb_ensemble_create(len(nb), nb.ctypes.data_as(ctypes.c_void_p),
+                                        *[a.ctypes.data_as(ctypes.c_void_p) for a in args],
+                                        None, None, ctypes.byref(h))
+    return rc, h
+
+
+def test_create_rejects_bad_input_before_device_work(fbmod):
+    m = np.array([1.0, 1e-3, 1e-3])
+    x = np.array([[0, 0, 0], [1.0, 0, 0], [2.0, 0, 0]])
+    v = np.zeros((3, 3))
+    rc, h = _create(fbmod, [3], -m, x, v)
+    assert rc == fbmod.E_INVAL and not h.value
+    assert b"mass" in fbmod.lib().fb_last_error()
+    x2 = x.copy(); x2[1, 1] = np.nan
+    rc, _ = _create(fbmod, [3], m, x2, v)
+    assert rc == fbmod.E_INVAL and b"finite" in fbmod.lib().fb_last_error()
+    rc, _ = _create(fbmod, [1, 2], m, x, v)
+    assert rc == fbmod.E_INVAL
+    rc, _ = _create(fbmod, [17], np.ones(17), np.zeros((17, 3)), np.zeros((17, 3)))
+    assert rc == fbmod.E_INVAL
+
+
+def test_null_handles(fbmod):
+    L = fbmod.lib()
+    assert L.fb_integrate_steps(None, 10, 0.1, None) == fbmod.E_INVAL
+    assert L.fb_integrate(None, 1.0, 0.1, None) == fbmod.E_INVAL
+    assert L.fb_get_state(None, None, None, None, None, None) == fbmod.E_INVAL
+    assert L.fb_diagnostics(None, None, None) == fbmod.E_INVAL
+    assert L.fb_ensemble_destroy(None) == fbmod.OK
+
+
+def test_plan_table(fbmod):
+    m0 = fbmod.get_plan(5)
+    fbmod.set_plan(5, fbmod.MAP_SPL, 2, 0)
+    assert fbmod.get_plan(5) == (fbmod.MAP_SPL, 2, 0)
+    fbmod.set_plan(5, m0[0], m0[1], m0[2])
+    with pytest.raises(fbmod.FewbodyError):
+        fbmod.set_plan(9, fbmod.MAP_SPL, 1, 0)      # SPL built for n <= 6 only
+    with pytest.raises(fbmod.FewbodyError):
+        fbmod.set_plan(1, fbmod.MAP_BPL, 1, 0)
+    with pytest.raises(fbmod.FewbodyError):
+        fbmod.set_plan(4, fbmod.MAP_BPL, 0, 0)
+
+
+def test_product_path_does_not_touch_the_oracle():
+    """The HIP binding, runtime and kernels never import or link the oracle."""
+    pkg = os.path.join(ROOT, "paper_1208_1157_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt and "hermite_oracle" not in txt, f

@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every case integrates seeded synthetic ensembles on the GPU and with the
+oracle from the same inputs and compares them system by system with the
+relative error of Section 5.2.1's test mode (1e-10).  Full-size workloads
+are checked on a sample of systems the oracle recomputes one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_1157_amd import gen
+from tests.helpers import REL_TOL, assert_parity, oracle_fixed, per_system_rel_err, threads
+
+pytestmark = pytest.mark.gpu
+
+H1000 = 2 * math.pi / 1000
+H2000 = 2 * math.pi / 2000
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture
+def plans(fb):
+    saved = {n: fb.get_plan(n) for n in [0] + list(range(2, 17))}
+    yield fb
+    for n, (m, w, g) in saved.items():
+        fb.set_plan(n, m, w, g)
+
+
+def run_gpu(fb, ens, steps, h, opts=None, host=False):
+    E = fb.from_gen(ens, host=host)
+    E.integrate_steps(steps, h, opts)
+    st = E.state()
+    acc, jerk, _ = E.hermite_state()
+    E.close()
+    return st, acc, jerk
+
+
+@pytest.mark.parametrize("mapping", ["spl", "bpl"])
+def test_parity_three_body_1024(plans, ora, mapping):
+    fb = plans
+    fb.set_plan(3, fb.MAP_SPL if mapping == "spl" else fb.MAP_BPL, 4 if mapping == "spl" else 2)
+    ens, p = gen.workload("parity_1024x3")
+    say("parity_1024x3", mapping, p)
+    st, acc, jerk = run_gpu(fb, ens, p["steps"], p["dt"])
+    X, V, A, J = oracle_fixed(ora, ens, p["dt"], p["steps"])
+    ex, ev = assert_parity(ens.n_body, st["pos"], st["vel"], X, V, label=mapping)
+    say("max rel err", ex, ev)
+    assert np.all(st["status"] == fb.DONE)
+    assert np.all(st["steps"] == p["steps"])
+    assert np.all(st["t"] == p["steps"] * p["dt"])
+    assert per_system_rel_err(ens.n_body, acc, A).max() < 1e-9
+    assert per_system_rel_err(ens.n_body, jerk, J).max() < 1e-9
+
+
+@pytest.mark.parametrize("sched", ["plain", "persistent", "persistent_compact"])
+@pytest.mark.parametrize("mapping", ["spl", "bpl"])
+def test_parity_ragged_all_body_counts(plans, ora, sched, mapping):
+    """n = 2..16 with ragged tails in every bucket, both mappings (SPL where
+    built), both schedules, quanta that do not divide the step count."""
+    fb = plans
+    for n in range(2, 17):
+        use_spl = mapping == "spl" and n <= 6
+        fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
+    ens = gen.ragged_hill(400, seed=7, n_lo=2, n_hi=16)
+    steps = 300
+    opts = None
+    if sched != "plain":
+        opts = fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=70,
+                       compact=(sched == "persistent_compact"))
+    say("ragged 2..16", sched, mapping)
+    st, _, _ = run_gpu(fb, ens, steps, H2000, opts)
+    X, V, _, _ = oracle_fixed(ora, ens, H2000, steps)
+    assert_parity(ens.n_body, st["pos"], st["vel"], X, V, label=f"{sched}/{mapping}")
+    assert np.all(st["steps"] == steps) and np.all(st["status"] == fb.DONE)
+
+
+def test_parity_full_size_three_body_sampled(plans, ora):
+    """131072 systems (the headline ensemble) in the benchmark's launch
+    configuration; 1000 steps; 384 sampled systems recomputed by the oracle."""
+    fb = plans
+    ens, p = gen.workload("homog_131072x3")
+    say("homog_131072x3 sampled, 1000 steps")
+    st, _, _ = run_gpu(fb, ens, 1000, p["dt"])
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(ens.n_sys, 384, replace=False))
+    idx[0], idx[-1] = 0, ens.n_sys - 1
+    sub = ens.subset(idx)
+    X, V, _, _ = oracle_fixed(ora, sub, p["dt"], 1000)
+    rows = np.concatenate([np.arange(3 * s, 3 * s + 3) for s in idx])
+    assert_parity(sub.n_body, st["pos"][rows], st["vel"][rows], X, V, label="131072 sampled")
+    assert np.all(st["status"] == fb.DONE)
+
+
+def test_parity_full_size_ragged_sampled(plans, ora):
+    """65536 ragged systems (n 3..15) through the persistent schedule; sampled."""
+    fb = plans
+    ens, p = gen.workload("ragged_65536x3-15")
+    steps = 200
+    say("ragged_65536 sampled, persistent, 200 steps")
+    opts = fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=64, compact=True)
+    st, _, _ = run_gpu(fb, ens, steps, p["dt"], opts)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(ens.n_sys, 256, replace=False))
+    sub = ens.subset(idx)
+    off = ens.offsets
+    rows = np.concatenate([np.arange(off[s], off[s + 1]) for s in idx])
+    X, V, _, _ = oracle_fixed(ora, sub, p["dt"], steps)
+    assert_parity(sub.n_body, st["pos"][rows], st["vel"][rows], X, V, label="65536 ragged sampled")
+
+
+@pytest.mark.parametrize("steps", [1000, 20000])
+def test_energy_drift_within_twice_oracle(fb, ora, steps):
+    """Energy drift |dE/E| of the GPU run within 2x the oracle's, over the
+    ensemble (max and RMS over systems, floor 1e-14).  Per-system values at
+    short horizons are roundoff noise, so the bar applies to the ensemble."""
+    ens, p = gen.workload("parity_1024x3", n_sys=256)
+    say("energy drift 256x3", steps)
+    st, _, _ = run_gpu(fb, ens, steps, p["dt"])
+    X, V, _, _ = oracle_fixed(ora, ens, p["dt"], steps)
+    E0, _ = ora.ensemble_energy(ens.n_body, ens.mass, ens.pos, ens.vel)
+    Eg, _ = ora.ensemble_energy(ens.n_body, ens.mass, st["pos"], st["vel"])
+    Eo, _ = ora.ensemble_energy(ens.n_body, ens.mass, X, V)
+    dg = np.abs((Eg - E0) / E0)
+    do = np.abs((Eo - E0) / E0)
+    say("drift max gpu/oracle", dg.max(), do.max(), "rms", np.sqrt((dg ** 2).mean()), np.sqrt((do ** 2).mean()))
+    assert dg.max() <= max(2 * do.max(), 1e-14)
+    assert np.sqrt((dg ** 2).mean()) <= max(2 * np.sqrt((do ** 2).mean()), 1e-14)
+
+
+def test_diagnostics_kernel_matches_oracle(fb, ora):
+    ens = gen.ragged_hill(200, seed=3, n_lo=2, n_hi=16)
+    say("diagnostics 200 ragged")
+    E = fb.from_gen(ens)
+    e, L = E.diagnostics()
+    E.close()
+    eo, Lo = ora.ensemble_energy(ens.n_body, ens.mass, ens.pos, ens.vel)
+    assert np.all(np.abs(e - eo) <= 1e-13 * np.abs(eo))
+    assert np.all(np.abs(L - Lo).max(axis=1) <= 1e-13 * np.abs(Lo).max(axis=1))
+
+
+def test_host_and_device_create_agree_bitwise(fb):
+    ens = gen.ragged_hill(100, seed=9, n_lo=2, n_hi=16)
+    say("host vs device create")
+    a, _, _ = run_gpu(fb, ens, 50, H2000, host=True)
+    b, _, _ = run_gpu(fb, ens, 50, H2000, host=False)
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+
+
+def test_determinism_and_chunking_invariance(fb):
+    ens, p = gen.workload("parity_1024x3", n_sys=512)
+    say("determinism + chunking 512x3")
+    a, _, _ = run_gpu(fb, ens, 400, p["dt"])
+    b, _, _ = run_gpu(fb, ens, 400, p["dt"])
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    E = fb.from_gen(ens)
+    for _ in range(4):
+        E.integrate_steps(100, p["dt"])
+    c = E.state()
+    E.close()
+    assert np.array_equal(a["pos"], c["pos"]) and np.array_equal(a["vel"], c["vel"])
+    assert np.allclose(c["t"], 400 * p["dt"], rtol=1e-14, atol=0)
+    assert np.all(c["steps"] == 400)
+
+
+def test_persistent_equals_plain_bitwise(plans):
+    fb = plans
+    ens = gen.ragged_hill(300, seed=11, n_lo=3, n_hi=12)
+    say("persistent vs plain bitwise")
+    a, _, _ = run_gpu(fb, ens, 150, H2000)
+    for compact in (False, True):
+        o = fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=40, compact=compact)
+        b, _, _ = run_gpu(fb, ens, 150, H2000, o)
+        assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+
+
+def test_time_reversal(fb):
+    ens, p = gen.workload("parity_1024x3", n_sys=128)
+    say("time reversal 128x3")
+    E = fb.from_gen(ens)
+    E.integrate_steps(1000, p["dt"])
+    E.integrate_steps(1000, -p["dt"])
+    st = E.state()
+    E.close()
+    assert np.abs(st["pos"] - ens.pos).max() < 1e-11
+    assert np.abs(st["vel"] - ens.vel).max() < 1e-11
+    assert np.all(np.abs(st["t"]) < 1e-12)
+
+
+def test_integrate_to_t_end_with_short_last_step(fb, ora):
+    ens, p = gen.workload("parity_1024x3", n_sys=64)
+    h = p["dt"]
+    t_end = 2 * math.pi * 1.2345
+    nfull = int(math.floor(t_end / h))
+    say("to t_end", t_end, nfull)
+    E = fb.from_gen(ens)
+    E.integrate(t_end, h)
+    st = E.state()
+    E.close()
+    X, V, A, J = ora.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, h, nfull, nthreads=threads())
+    h_last = t_end - nfull * h
+    off = ens.offsets
+    Xf, Vf = X.copy(), V.copy()
+    for s in range(ens.n_sys):
+        sl = slice(off[s], off[s + 1])
+        Xf[sl], Vf[sl], _, _ = ora.integrate_fixed(ens.mass[sl], X[sl], V[sl], h_last, 1, acc=A[sl], jerk=J[sl])
+    assert_parity(ens.n_body, st["pos"], st["vel"], Xf, Vf, label="t_end")
+    assert np.all(st["t"] == t_end) and np.all(st["steps"] == nfull + 1)
+
+
+def test_empty_ensemble(fb):
+    say("empty ensemble")
+    E = fb.Ensemble(np.zeros(0, np.int32), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)))
+    E.integrate_steps(10, 0.01)
+    st = E.state()
+    assert st["pos"].shape == (0, 3)
+    E.close()
+
+
+def test_nonfinite_system_is_isolated(fb, ora):
+    ens = gen.ragged_hill(40, seed=5, n_lo=3, n_hi=6)
+    off = ens.offsets
+    pos = ens.pos.copy()
+    bad = 17
+    pos[off[bad] + 1] = pos[off[bad] + 2]         # coincident planets
+    say("nonfinite isolation")
+    E = fb.Ensemble(ens.n_body, ens.mass, pos, ens.vel)
+    E.integrate_steps(20, H2000)
+    st = E.state()
+    E.close()
+    assert st["status"][bad] == fb.NONFINITE
+    others = np.arange(ens.n_sys) != bad
+    assert np.all(st["status"][others] == fb.DONE)
+    good = ens.subset(np.nonzero(others)[0])
+    X, V, _, _ = oracle_fixed(ora, good, H2000, 20)
+    rows = np.concatenate([np.arange(off[s], off[s + 1]) for s in np.nonzero(others)[0]])
+    assert_parity(good.n_body, st["pos"][rows], st["vel"][rows], X, V, label="isolation")
+
+
+def test_invalid_device_inputs_rejected(fb):
+    m = np.array([1.0, -1e-3, 1e-3])
+    x = np.array([[0, 0, 0], [1.0, 0, 0], [2.0, 0, 0]])
+    say("invalid device input")
+    with pytest.raises(fb.FewbodyError) as ei:
+        fb.Ensemble([3], m, x, np.zeros((3, 3)))
+    assert ei.value.code == fb.E_INVAL
+
+
+def _adaptive_case(plans, ora, mapping, n_sys, orbits):
+    fb = plans
+    for n in range(4, 9):
+        use_spl = mapping == "spl" and n <= 6
+        fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
+    ens, p = gen.workload("lifetimes_65536x4-8", n_sys=n_sys)
+    t_end = 2 * math.pi * orbits
+    say("adaptive", mapping, n_sys, "systems to t =", t_end)
+    E = fb.from_gen(ens)
+    E.integrate(t_end, 0.0, fb.Opts(adaptive=True, eta=p["eta"], stop_rules=3, r_eject=p["r_eject"]))
+    st = E.state()
+    E.close()
+    outs = [ora.integrate_adaptive(*ens.system(s), t_end=t_end, eta=p["eta"], stop_rules=3,
+                                   r_eject=p["r_eject"]) for s in range(ens.n_sys)]
+    return fb, ens, st, outs, t_end
+
+
+@pytest.mark.parametrize("mapping", ["spl", "bpl"])
+def test_adaptive_with_stop_rules_parity(plans, ora, mapping):
+    """Adaptive step + both stop rules on the uneven-lifetimes distribution
+    (tight, eccentric, chaotic systems) over a 5-orbit horizon: systems whose
+    discrete decisions agree with the oracle (final status, step count) match
+    it to 1e-10 relative; decisions may flip only on last-bit differences."""
+    fb, ens, st, outs, t_end = _adaptive_case(plans, ora, mapping, 128, 5)
+    off = ens.offsets
+    agree, worst = 0, 0.0
+    for s, o in enumerate(outs):
+        if o["status"] != st["status"][s] or o["steps"] != st["steps"][s]:
+            continue
+        agree += 1
+        sl = slice(off[s], off[s + 1])
+        ex = per_system_rel_err([ens.n_body[s]], st["pos"][sl], o["pos"])[0]
+        ev = per_system_rel_err([ens.n_body[s]], st["vel"][sl], o["vel"])[0]
+        worst = max(worst, ex, ev)
+        if o["status"] == ora.DONE:
+            assert st["t"][s] == t_end
+    say("agree", agree, "of", ens.n_sys, "worst rel err", worst)
+    assert agree >= 0.97 * ens.n_sys, agree
+    assert worst <= REL_TOL, worst
+
+
+def test_adaptive_decisions_agree_long_horizon(plans, ora):
+    """Over 30 orbits the same systems retire for the same reason; step counts
+    agree within 1% where the status agrees (chaos amplifies last-bit step
+    differences, so trajectories are not compared here)."""
+    fb, ens, st, outs, _ = _adaptive_case(plans, ora, "bpl", 96, 30)
+    same = sum(o["status"] == st["status"][s] for s, o in enumerate(outs))
+    close = sum(o["status"] == st["status"][s] and abs(o["steps"] - st["steps"][s]) <= 0.01 * o["steps"]
+                for s, o in enumerate(outs))
+    say("status agree", same, "steps within 1%", close, "of", ens.n_sys)
+    assert same >= 0.95 * ens.n_sys and close >= 0.9 * ens.n_sys
