@@ -11,9 +11,14 @@ timed steps.
 Printed as one JSON line, with
   roofline      achieved algorithmic FP64 FLOP/s of the integration kernel
                 (HIP events on its launch stream) against the FP64 vector peak;
+  p50/p99       solve latency of the serving trace (Poisson arrivals at
+                200 req/s, 1..4096 systems of 3..10 bodies per request);
   cpu_baseline  the CPU oracle timed on this host's cores on a bounded sample;
-  extras        the ragged-batch comparison (plain per-bucket launches vs the
-                fused persistent launch) when --extras is given.
+  extras        ragged 65536 x (3..15): autotuned plans, plain per-bucket
+                launches vs the fused persistent launch; uneven lifetimes
+                65536 x (4..8) with adaptive steps and stop rules on a bounded
+                horizon: plain launches vs persistent quanta with compaction;
+                the serving report.
 """
 from __future__ import annotations
 
@@ -77,28 +82,76 @@ def cpu_baseline(ens, h, target_s=12.0):
                       f"{dt:.1f} s, std::thread-free pthreads static partition"}
 
 
-def ragged_extras(fb, gen, torch, steps_cap=None):
-    """Ragged 65536 x (3..15) batch: plain (one launch per body-count bucket,
-    sequential) vs the fused persistent launch."""
+def timed(fb, torch, ens, fn):
+    E = fb.from_gen(ens)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn(E)
+    E.synchronize()
+    dt = time.perf_counter() - t0
+    st = E.state()
+    E.close()
+    return dt, st
+
+
+def ragged_extras(fb, gen, torch, log):
+    """Ragged 65536 x (3..15) batch: autotuned plans, then plain (one launch
+    per body-count bucket, sequential) vs the fused persistent launch."""
+    from paper_1208_1157_amd import autotune
     ens, p = gen.workload("ragged_65536x3-15")
-    nsteps = steps_cap or p["steps"]
+    nsteps = p["steps"]
+    tune = autotune.tune(fb, ens, p["dt"], use_cache=False, log=log)
     out = {"workload": f"ragged_65536x3-15: {ens.n_sys} systems, n uniform 3..15, "
-                       f"{nsteps} fixed steps of 2pi/2000"}
+                       f"{nsteps} fixed steps of 2pi/2000",
+           "autotune_seconds": tune["seconds"], "plans": tune["plans"],
+           "calibration_steps": tune.get("calibration_steps")}
     useful = ens.n_sys * nsteps
     flops = float(sum(flops_per_system_step(int(n)) for n in ens.n_body)) * nsteps
     for name, opts in [("plain", fb.Opts()),
                        ("persistent", fb.Opts(schedule=fb.SCHED_PERSISTENT))]:
-        E = fb.from_gen(ens)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        E.integrate_steps(nsteps, p["dt"], opts)
-        E.synchronize()
-        dt = time.perf_counter() - t0
-        E.close()
+        dt, st = timed(fb, torch, ens, lambda E: E.integrate_steps(nsteps, p["dt"], opts))
+        assert (st["status"] == fb.DONE).all()
         out[name] = {"system_steps_per_s": useful / dt, "seconds": dt,
-                     "fp64_tflops": flops / dt / 1e12}
+                     "fp64_tflops_algorithmic": flops / dt / 1e12}
+        log(f"[bench] ragged {name}: {useful / dt:.3e} system-steps/s")
     out["persistent_over_plain"] = out["persistent"]["system_steps_per_s"] / out["plain"]["system_steps_per_s"]
     return out
+
+
+def lifetimes_extras(fb, gen, torch, log, orbits=100.0, quantum=2000):
+    """Uneven lifetimes 65536 x (4..8): adaptive steps (eta 0.01) with the
+    close-encounter and ejection rules, on a bounded horizon of `orbits`
+    inner orbits (the workload's 1e4 orbits would take hours).  Plain: one
+    launch per bucket, retired lanes idle until their wave's last system
+    ends; persistent: quanta with in-kernel compaction of retired systems."""
+    import numpy as np
+    ens, p = gen.workload("lifetimes_65536x4-8")
+    t_end = 2 * math.pi * orbits
+    base = dict(adaptive=True, eta=p["eta"], stop_rules=3, r_eject=p["r_eject"])
+    out = {"workload": f"lifetimes_65536x4-8: {ens.n_sys} systems, n uniform 4..8, adaptive eta={p['eta']}, "
+                       f"stop rules, bounded horizon t = 2pi*{orbits:g} (workload horizon 2pi*1e4)"}
+    for name, opts in [("plain", fb.Opts(**base)),
+                       ("persistent_compact", fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=quantum,
+                                                      compact=True, **base))]:
+        dt, st = timed(fb, torch, ens, lambda E: E.integrate(t_end, 0.0, opts))
+        useful = float(st["steps"].sum())
+        flops = float(sum(flops_per_system_step(int(n)) * float(k) for n, k in zip(ens.n_body, st["steps"])))
+        hist = {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))}
+        out[name] = {"useful_system_steps_per_s": useful / dt, "seconds": dt, "system_steps": useful,
+                     "fp64_tflops_algorithmic": flops / dt / 1e12, "status_histogram": hist}
+        log(f"[bench] lifetimes {name}: {useful / dt:.3e} useful system-steps/s in {dt:.2f} s")
+    out["compaction_over_plain"] = (out["persistent_compact"]["useful_system_steps_per_s"]
+                                    / out["plain"]["useful_system_steps_per_s"])
+    return out
+
+
+def serving_report(fb, gen, log, n_req=2000):
+    from paper_1208_1157_amd import serve
+    trace = gen.serving_trace(n_req, rate=200.0, seed=4)
+    rep = serve.run_trace(fb, trace, log=log)
+    rep["workload"] = (f"serving: {n_req} requests, Poisson 200 req/s, 1..4096 systems (log-uniform) of 3..10 "
+                       f"bodies, t_end 2pi*10^U(1,3), dt 2pi/1000")
+    return rep
 
 
 def main():
@@ -109,7 +162,11 @@ def main():
     ap.add_argument("--hermite-steps", type=int, default=100000,
                     help="Hermite steps per benchmark step (the workload's 100000)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--extras", action="store_true", help="also run the ragged plain-vs-persistent comparison")
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the ragged (autotuned, plain vs persistent) and uneven-lifetimes "
+                         "(plain vs compaction) comparisons")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -193,8 +250,20 @@ def main():
                      "kernel_launches": launches,
                      "flops_per_launch": flops_per_launch},
     }
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    extras = {}
+    if not args.no_serve:
+        rep = serving_report(fb, gen, log, args.serve_requests)
+        result["p50_latency_s"] = rep["p50_latency_s"]
+        result["p99_latency_s"] = rep["p99_latency_s"]
+        extras["serving"] = rep
     if args.extras:
-        result["extras"] = {"ragged": ragged_extras(fb, gen, torch)}
+        extras["ragged"] = ragged_extras(fb, gen, torch, log)
+        extras["lifetimes"] = lifetimes_extras(fb, gen, torch, log)
+    if extras:
+        result["extras"] = extras
     if not args.no_cpu:
         ens_cpu = ens
         result["cpu_baseline"] = cpu_baseline(ens_cpu, h)

@@ -191,6 +191,29 @@ fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group,
 fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
                       int32_t *groups_per_cu);
 
+/* Autotuner (the counterpart of the paper's automatic choice of systems per
+ * block under register/shared-memory/thread limits, Section 4.4, made by
+ * measurement as its Section 5.3 recommends).  On ensemble e, for every body
+ * count it holds, times `steps` fixed steps of dt with each candidate plan
+ * of the plain schedule (mapping x waves per group), then the fused
+ * persistent launch over the whole ensemble (waves per group x groups per
+ * CU), and installs the fastest as the plans (fb_set_plan).  The ensemble's
+ * state is restored afterwards.  out[0..max_out) receives every candidate
+ * timed (n = 0 for the persistent launch); *n_out their count.  Allocates a
+ * temporary copy of the ensemble's device state. */
+typedef struct {
+    int32_t n;                 /* body count; 0 = the persistent launch shape */
+    int32_t mapping;           /* FB_MAP_*                                    */
+    int32_t waves_per_group;
+    int32_t groups_per_cu;
+    double ms;                 /* elapsed time of the calibration run         */
+    int32_t chosen;            /* 1 if installed as the plan                  */
+    int32_t pad;
+} fb_tune_entry;
+
+fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *out,
+                      int32_t max_out, int32_t *n_out);
+
 /* ---------------------------------------------------------------- timing */
 /* When enabled, the library brackets each integration kernel it launches
  * with HIP events on the ensemble's stream and accumulates their elapsed
@@ -198,6 +221,77 @@ fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
  * the last reset. */
 fb_status fb_profile_enable(int32_t on);
 fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
+
+/* ---------------------------------------------------------------- serving */
+/* A continuous-batching integration server.  Requests (an ensemble with its
+ * own destination time and fixed step, integrated as fb_integrate does with
+ * the persistent schedule) are queued from any thread and served by one
+ * worker thread in quanta: queued requests are admitted in arrival order
+ * while their device state fits the memory budget and the resident cap;
+ * every quantum advances all resident systems by up to steps_per_quantum
+ * steps in one fused launch; finished requests are copied back and their
+ * memory is reused.  A request's results do not depend on what else is
+ * resident.  (No counterpart in the paper, whose host only sets up, loads,
+ * calls and examines -- Section 5.3; this is the serving form of its many
+ * steps per kernel call.) */
+typedef struct fb_server fb_server;
+
+enum { FB_REQ_QUEUED = 0, FB_REQ_RUNNING = 1, FB_REQ_DONE = 2, FB_REQ_CANCELLED = 3,
+       FB_REQ_FAILED = 4 };
+
+typedef struct {
+    size_t budget_bytes;        /* device memory for resident requests, allocated
+                                   once at creation (0: 4 GiB)                      */
+    int32_t max_resident;       /* requests resident at once (0: 256)               */
+    int32_t steps_per_quantum;  /* steps per resident system per quantum (0: 2000)  */
+} fb_server_opts;
+
+typedef struct {
+    int64_t submitted, admitted, completed, queued, resident, quanta;
+    double system_steps;        /* Hermite system-steps executed                    */
+    double busy_seconds;        /* wall time spent inside quanta                    */
+    size_t bytes_in_use, peak_bytes;
+} fb_server_stats;
+
+void fb_server_opts_default(fb_server_opts *o);
+
+/* Create a server on the current device.  hip_stream: the stream the worker
+ * enqueues on (borrowed; NULL: the server creates its own).  Allocates the
+ * whole budget up front; FB_E_NOMEM if that fails. */
+fb_status fb_server_create(const fb_server_opts *o, void *hip_stream, fb_server **out);
+
+/* Queue a request; the host arrays are copied before the call returns
+ * (layout as fb_ensemble_create, t0 = 0).  Integrates every system to t_end
+ * with fixed step dt.  *req_id identifies it.  FB_E_INVAL on bad input,
+ * FB_E_BUDGET if its state alone exceeds the budget. */
+fb_status fb_server_submit(fb_server *s, int32_t n_sys, const int32_t *n_body,
+                           const double *mass, const double *pos, const double *vel,
+                           double t_end, double dt, int64_t *req_id);
+
+/* Current FB_REQ_* state of a request. */
+fb_status fb_server_poll(fb_server *s, int64_t req_id, int32_t *state);
+
+/* Block until the request is DONE, CANCELLED or FAILED, or timeout_s
+ * seconds pass (< 0: no limit); *state (may be NULL) gets its state. */
+fb_status fb_server_wait(fb_server *s, int64_t req_id, double timeout_s, int32_t *state);
+
+/* Results of a DONE request into HOST arrays (any may be NULL; shapes as
+ * fb_get_state), and times[3] = submit, admission and completion times on
+ * the fb_monotonic_seconds clock.  Releases the request: a second call
+ * returns FB_E_NOTFOUND.  FB_E_STATE if it is not done. */
+fb_status fb_server_result(fb_server *s, int64_t req_id, double *pos, double *vel,
+                           double *t, int32_t *status, int64_t *steps, double *times);
+
+/* Cancel a queued or running request (it settles as CANCELLED). */
+fb_status fb_server_cancel(fb_server *s, int64_t req_id);
+
+fb_status fb_server_get_stats(fb_server *s, fb_server_stats *out);
+
+/* Stop the worker (resident work is abandoned) and free the server. */
+fb_status fb_server_destroy(fb_server *s);
+
+/* Seconds on the host monotonic clock (CLOCK_MONOTONIC) used for times. */
+double fb_monotonic_seconds(void);
 
 /* ---------------------------------------------------------------- misc */
 const char *fb_last_error(void);

@@ -19,12 +19,12 @@
 // In both, each body sums its planet partners in ascending order and the
 // star last (Section 4.2).
 //
-// The corrector uses the algebraically equivalent "x0 form" of Eq. 4 (read
-// with coefficient 3/20, a (dt)^3 jerk term and the predicted state as
-// base): v1 = v0 + h/2 (a0 + a1) + h^2/12 (j0 - j1),
-// x1 = x0 + h/2 (v0 + v1) + h^2/10 (a0 - a1) + h^3/120 (j0 + j1),
-// with the a0/j0 parts folded into per-step bases so each correction costs
-// five FMAs per component.
+// The corrector is Eq. 4 read with coefficient 3/20, a (dt)^3 jerk term and
+// the predicted state (xp, vp) as the base of every correction:
+//   x1 = xp - 3/20 (a0 - ak) h^2 - (7 j0 + 2 jk) h^3 / 60
+//   v1 = vp - 1/2 (a0 - ak) h - (5 j0 + jk) h^2 / 12
+// The a0/j0 parts are folded into per-step bases, so each correction costs
+// four FMAs per component and does not need the corrected velocity.
 #include "fb_internal.h"
 
 #include <climits>
@@ -57,17 +57,16 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 1/sqrt(x): hardware estimate (v_rsq_f64) refined by two Newton-Raphson
-// steps y <- y + (y/2)(1 - x y^2), which converge quadratically from the
-// estimate's error to FP64 rounding level.
+// 1/sqrt(x): hardware estimate y (v_rsq_f64, relative error ~6e-8 on
+// gfx950) refined by one third-order step of the series
+// 1/sqrt(x) = y (1 - e)^(-1/2) = y (1 + e/2 + 3e^2/8 + ...), e = 1 - x y^2,
+// whose truncation (~e^3) is far below FP64 rounding.
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    const double p = fma(0.375, e, 0.5);
+    return fma(y * e, p, y);
 }
 
 __device__ __forceinline__ bool finite3(const double (&p)[3])
@@ -77,8 +76,9 @@ __device__ __forceinline__ bool finite3(const double (&p)[3])
 
 // Step coefficients of the predictor (Eq. 3) and corrector (Eq. 4).
 struct Coef {
-    double h, hh2, hhh6;       // h, h^2/2, h^3/6
-    double c1, c2, c3, c4;     // h/2, h^2/12, h^2/10, h^3/120
+    double h, hh2, hhh6;       // predictor: h, h^2/2, h^3/6
+    double bxa, bxj, bva, bvj; // bases: -3/20 h^2, -7/60 h^3, -h/2, -5/12 h^2
+    double cxa, cxj, cva, cvj; // corrections: 3/20 h^2, -h^3/30, h/2, -h^2/12
 };
 
 __device__ __forceinline__ Coef make_coef(double h)
@@ -88,10 +88,14 @@ __device__ __forceinline__ Coef make_coef(double h)
     k.h = h;
     k.hh2 = 0.5 * h2;
     k.hhh6 = h3 * (1.0 / 6.0);
-    k.c1 = 0.5 * h;
-    k.c2 = h2 * (1.0 / 12.0);
-    k.c3 = h2 * 0.1;
-    k.c4 = h3 * (1.0 / 120.0);
+    k.cxa = 0.15 * h2;
+    k.cxj = h3 * (-1.0 / 30.0);
+    k.cva = 0.5 * h;
+    k.cvj = h2 * (-1.0 / 12.0);
+    k.bxa = -k.cxa;
+    k.bxj = h3 * (-7.0 / 60.0);
+    k.bva = -k.cva;
+    k.bvj = h2 * (-5.0 / 12.0);
     return k;
 }
 
@@ -102,16 +106,16 @@ __device__ __forceinline__ void predict_comp(const Coef &k, double x, double v, 
 {
     xp = fma(k.hhh6, j, fma(k.hh2, a, fma(k.h, v, x)));
     vp = fma(k.hh2, j, fma(k.h, a, v));
-    bx = fma(k.c4, j, fma(k.c3, a, fma(k.c1, v, x)));
-    bv = fma(k.c2, j, fma(k.c1, a, v));
+    bx = fma(k.bxj, j, fma(k.bxa, a, xp));
+    bv = fma(k.bvj, j, fma(k.bva, a, vp));
 }
 
 // One correction of one component from the latest evaluation (ak, jk).
 __device__ __forceinline__ void correct_comp(const Coef &k, double bx, double bv, double ak,
                                              double jk, double &xc, double &vc)
 {
-    vc = fma(-k.c2, jk, fma(k.c1, ak, bv));
-    xc = fma(k.c4, jk, fma(-k.c3, ak, fma(k.c1, vc, bx)));
+    xc = fma(k.cxj, jk, fma(k.cxa, ak, bx));
+    vc = fma(k.cvj, jk, fma(k.cva, ak, bv));
 }
 
 // ---------------------------------------------------------------------------
@@ -248,20 +252,21 @@ __device__ __forceinline__ void spl_pair(const int i, const int j, const double 
     const double ri2 = ri * ri;
     const double ri3 = ri2 * ri;
     const double al = 3.0 * ru * ri2;
-    const double Ax = rx * ri3, Ay = ry * ri3, Az = rz * ri3;
-    const double Jx = fma(-al, Ax, ux * ri3), Jy = fma(-al, Ay, uy * ri3), Jz = fma(-al, Az, uz * ri3);
-    a[i][0] = fma(m[j], Ax, a[i][0]);
-    a[i][1] = fma(m[j], Ay, a[i][1]);
-    a[i][2] = fma(m[j], Az, a[i][2]);
-    a[j][0] = fma(-m[i], Ax, a[j][0]);
-    a[j][1] = fma(-m[i], Ay, a[j][1]);
-    a[j][2] = fma(-m[i], Az, a[j][2]);
-    jk[i][0] = fma(m[j], Jx, jk[i][0]);
-    jk[i][1] = fma(m[j], Jy, jk[i][1]);
-    jk[i][2] = fma(m[j], Jz, jk[i][2]);
-    jk[j][0] = fma(-m[i], Jx, jk[j][0]);
-    jk[j][1] = fma(-m[i], Jy, jk[j][1]);
-    jk[j][2] = fma(-m[i], Jz, jk[j][2]);
+    // J / |r|^-3 = u - 3 (r.u)/|r|^2 r; masses folded into |r|^-3
+    const double wx = fma(-al, rx, ux), wy = fma(-al, ry, uy), wz = fma(-al, rz, uz);
+    const double mj3 = m[j] * ri3, mi3 = m[i] * ri3;
+    a[i][0] = fma(mj3, rx, a[i][0]);
+    a[i][1] = fma(mj3, ry, a[i][1]);
+    a[i][2] = fma(mj3, rz, a[i][2]);
+    a[j][0] = fma(-mi3, rx, a[j][0]);
+    a[j][1] = fma(-mi3, ry, a[j][1]);
+    a[j][2] = fma(-mi3, rz, a[j][2]);
+    jk[i][0] = fma(mj3, wx, jk[i][0]);
+    jk[i][1] = fma(mj3, wy, jk[i][1]);
+    jk[i][2] = fma(mj3, wz, jk[i][2]);
+    jk[j][0] = fma(-mi3, wx, jk[j][0]);
+    jk[j][1] = fma(-mi3, wy, jk[j][1]);
+    jk[j][2] = fma(-mi3, wz, jk[j][2]);
     if (TS) {
         const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
         wmax = fmax(wmax, fma(al, ru, u2) * ri2);
@@ -298,9 +303,8 @@ __device__ __forceinline__ void spl_accjerk(const double (&m)[N], const double (
 template <int N, bool TS>
 __device__ __forceinline__ double spl_step(const double (&m)[N], double (&x)[N][3],
                                            double (&v)[N][3], double (&a)[N][3],
-                                           double (&jk)[N][3], double h)
+                                           double (&jk)[N][3], const Coef &k)
 {
-    const Coef k = make_coef(h);
     double bx[N][3], bv[N][3], xc[N][3], vc[N][3];
 #pragma unroll
     for (int b = 0; b < N; ++b)
@@ -401,12 +405,38 @@ __device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
             jk[b][cc] = st[((R_J + cc) * N + b) * pitch + slot];
         }
     }
-    for (int q = 0; q < P.quantum; ++q) {
+    int quantum = P.quantum;
+    if (!ADV) {
+        // whole steps of the run with no per-step bookkeeping
+        long long whole = c.nfull - c.k;
+        whole = whole < 0 ? 0 : whole;
+        whole = min(whole, (long long)quantum);
+        whole = min(whole, P.max_steps - c.steps);
+        const int nrun = whole > 0 ? (int)whole : 0;
+        const Coef k = make_coef(c.dt);
+#pragma unroll 2
+        for (int q = 0; q < nrun; ++q)
+            (void)spl_step<N, false>(m, x, v, a, jk, k);
+        if (nrun > 0) {
+            c.k += nrun;
+            c.steps += nrun;
+            c.t = fma((double)c.k, c.dt, c.t0);
+            if (c.k >= c.nfull) {
+                const double rem = c.t_end - c.t;
+                if (!(rem * c.dt > 1e-9 * c.dt * c.dt)) {
+                    c.t = c.t_end;
+                    c.status = ST_DONE;
+                }
+            }
+        }
+        quantum -= nrun;
+    }
+    for (int q = 0; q < quantum; ++q) {
         double h = 0.0;
         bool last = false;
         if (!plan_step(c, P, h, last))
             break;
-        const double w = spl_step<N, ADV>(m, x, v, a, jk, h);
+        const double w = spl_step<N, ADV>(m, x, v, a, jk, make_coef(h));
         const double dtp = ADV ? P.eta * rsqrt_nr(w) : 0.0;
         finish_step(c, P, last, h, dtp);
         if (ADV) {

@@ -23,13 +23,20 @@
 #include <string>
 #include <vector>
 
+#include "fb_runtime_internal.h"
+
 using namespace fb;
+using namespace fb::rt;
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
 namespace {
 thread_local std::string g_err;
+}  // namespace
+
+namespace fb {
+namespace rt {
 
 fb_status fail(fb_status code, const char *fmt, ...)
 {
@@ -48,22 +55,10 @@ fb_status hip_fail(hipError_t e, const char *what)
                 hipGetErrorString(e));
 }
 
-#define FB_HIP(call)                                  \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess)                         \
-            return hip_fail(e_, #call);               \
-    } while (0)
-
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
-struct Plan {
-    int mapping;          // MAP_SPL / MAP_BPL
-    int waves_per_group;  // 1..4
-    int groups_per_cu;    // persistent schedule only (entry 0)
-};
-
+namespace {
 std::mutex g_plan_mu;
 Plan g_plan[kMaxBodies + 1];
 bool g_plan_init = false;
@@ -77,6 +72,7 @@ void init_plans_locked()
     g_plan[0] = Plan{MAP_BPL, 2, 8};
     g_plan_init = true;
 }
+}  // namespace
 
 Plan get_plan(int n)
 {
@@ -97,10 +93,7 @@ std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
 double g_prof_ms = 0.0;
 int64_t g_prof_launches = 0;
 
-struct ProfScope {
-    hipEvent_t a = nullptr, b = nullptr;
-    hipStream_t s;
-    explicit ProfScope(hipStream_t st) : s(st)
+ProfScope::ProfScope(hipStream_t st) : s(st)
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof_on)
@@ -111,7 +104,8 @@ struct ProfScope {
         }
         (void)hipEventRecord(a, s);
     }
-    ~ProfScope()
+
+ProfScope::~ProfScope()
     {
         if (!a)
             return;
@@ -119,27 +113,10 @@ struct ProfScope {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof_events.emplace_back(a, b);
     }
-};
 
 // ---------------------------------------------------------------------------
 // layout
 // ---------------------------------------------------------------------------
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-struct BucketLayout {
-    int n, count, pitch;
-    size_t st, t, t_end, dt, dtn, t0run, krun, nfull, steps, status, orig;   // byte offsets
-};
-
-struct Layout {
-    std::vector<BucketLayout> b;
-    int64_t n_bodies = 0;
-    int max_tiles = 0;
-    int list_total = 0;
-    size_t buckets, orig_off, staging, diag, ints, tiles, lists0, lists1, list_base, counts0,
-        counts1, order, mapping, total;
-};
-
 // Returns false for an invalid shape.
 bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L)
 {
@@ -203,7 +180,44 @@ bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L)
     return true;
 }
 
-}  // namespace
+std::vector<Bucket> bucket_views(char *base, const Layout &L)
+{
+    std::vector<Bucket> out;
+    for (const BucketLayout &bl : L.b) {
+        Bucket B;
+        B.st = reinterpret_cast<double *>(base + bl.st);
+        B.t = reinterpret_cast<double *>(base + bl.t);
+        B.t_end = reinterpret_cast<double *>(base + bl.t_end);
+        B.dt = reinterpret_cast<double *>(base + bl.dt);
+        B.dtn = reinterpret_cast<double *>(base + bl.dtn);
+        B.t0run = reinterpret_cast<double *>(base + bl.t0run);
+        B.krun = reinterpret_cast<long long *>(base + bl.krun);
+        B.nfull = reinterpret_cast<long long *>(base + bl.nfull);
+        B.steps = reinterpret_cast<long long *>(base + bl.steps);
+        B.status = reinterpret_cast<int *>(base + bl.status);
+        B.orig = reinterpret_cast<int *>(base + bl.orig);
+        B.n = bl.n;
+        B.pitch = bl.pitch;
+        B.count = bl.count;
+        B.pad = 0;
+        out.push_back(B);
+    }
+    return out;
+}
+
+std::vector<int> slot_origins(const std::vector<int32_t> &n_body, const Bucket &B)
+{
+    std::vector<int> v;
+    v.reserve(B.pitch);
+    for (size_t s = 0; s < n_body.size(); ++s)
+        if (n_body[s] == B.n)
+            v.push_back((int)s);
+    v.resize(B.pitch, 0);
+    return v;
+}
+
+}  // namespace rt
+}  // namespace fb
 
 // ---------------------------------------------------------------------------
 // ensemble object
@@ -243,26 +257,7 @@ T *at(fb_ensemble *e, size_t off)
 
 fb_status bind_layout(fb_ensemble *e)
 {
-    e->buckets.clear();
-    for (const BucketLayout &bl : e->L.b) {
-        Bucket B;
-        B.st = at<double>(e, bl.st);
-        B.t = at<double>(e, bl.t);
-        B.t_end = at<double>(e, bl.t_end);
-        B.dt = at<double>(e, bl.dt);
-        B.dtn = at<double>(e, bl.dtn);
-        B.t0run = at<double>(e, bl.t0run);
-        B.krun = at<long long>(e, bl.krun);
-        B.nfull = at<long long>(e, bl.nfull);
-        B.steps = at<long long>(e, bl.steps);
-        B.status = at<int>(e, bl.status);
-        B.orig = at<int>(e, bl.orig);
-        B.n = bl.n;
-        B.pitch = bl.pitch;
-        B.count = bl.count;
-        B.pad = 0;
-        e->buckets.push_back(B);
-    }
+    e->buckets = bucket_views(e->base, e->L);
     e->d_buckets = at<Bucket>(e, e->L.buckets);
     e->d_orig_off = at<long long>(e, e->L.orig_off);
     e->d_staging = at<double>(e, e->L.staging);
@@ -288,18 +283,15 @@ fb_status upload_tables(fb_ensemble *e)
     std::vector<long long> off(ns + 1, 0);
     for (int s = 0; s < ns; ++s)
         off[s + 1] = off[s] + e->n_body[s];
-    std::vector<int> fill[kMaxBodies + 1];
-    for (int s = 0; s < ns; ++s)
-        fill[e->n_body[s]].push_back(s);
     FB_HIP(hipMemcpyAsync(e->d_orig_off, off.data(), sizeof(long long) * (ns + 1),
                           hipMemcpyHostToDevice, e->stream));
     std::vector<int> list_base;
     int acc = 0;
+    std::vector<std::vector<int>> origins;
     for (const Bucket &B : e->buckets) {
-        std::vector<int> &v = fill[B.n];
-        v.resize(B.pitch, 0);
-        FB_HIP(hipMemcpyAsync(B.orig, v.data(), sizeof(int) * B.pitch, hipMemcpyHostToDevice,
-                              e->stream));
+        origins.push_back(slot_origins(e->n_body, B));
+        FB_HIP(hipMemcpyAsync(B.orig, origins.back().data(), sizeof(int) * B.pitch,
+                              hipMemcpyHostToDevice, e->stream));
         list_base.push_back(acc);
         acc += B.pitch;
     }
@@ -884,6 +876,142 @@ fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
     if (groups_per_cu)
         *groups_per_cu = p.groups_per_cu;
     return FB_OK;
+}
+
+fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *out,
+                      int32_t max_out, int32_t *n_out)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    if (steps < 1 || !(std::isfinite(dt) && dt != 0.0))
+        return fail(FB_E_INVAL, "steps must be >= 1 and dt finite, non-zero");
+    if (n_out)
+        *n_out = 0;
+    if (e->n_sys == 0)
+        return FB_OK;
+    const size_t total = e->L.total;
+    char *backup = nullptr;
+    FB_HIP(hipStreamSynchronize(e->stream));
+    FB_HIP(hipMalloc((void **)&backup, total));
+    std::vector<fb_tune_entry> entries;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    fb_status result = FB_OK;
+    auto run = [&]() -> fb_status {
+        FB_HIP(hipEventCreate(&ev0));
+        FB_HIP(hipEventCreate(&ev1));
+        FB_HIP(hipMemcpyAsync(backup, e->base, total, hipMemcpyDeviceToDevice, e->stream));
+        auto restore = [&]() -> hipError_t {
+            return hipMemcpyAsync(e->base, backup, total, hipMemcpyDeviceToDevice, e->stream);
+        };
+        StepParams P;
+        fb_opts o;
+        fb_opts_default(&o);
+        P = make_params(o, INT_MAX);
+        // plain schedule: per bucket, mapping x waves per group
+        for (const Bucket &B : e->buckets) {
+            struct Cand { int map, W; };
+            std::vector<Cand> cands;
+            for (int W : {1, 2, 4}) {
+                if (B.n <= kMaxSplBodies)
+                    cands.push_back({MAP_SPL, W});
+                cands.push_back({MAP_BPL, W});
+            }
+            double best = 1e300;
+            size_t best_i = 0;
+            for (const Cand &c : cands) {
+                FB_HIP(restore());
+                FB_HIP(launch_begin_run(B, 1, 1, 0.0, dt, 0, 0.0, e->stream));
+                FB_HIP(launch_plain(B, c.map, c.W, P, e->stream));   // warm-up (code load)
+                FB_HIP(restore());
+                FB_HIP(launch_begin_run(B, 1, steps, 0.0, dt, 0, 0.0, e->stream));
+                FB_HIP(hipEventRecord(ev0, e->stream));
+                FB_HIP(launch_plain(B, c.map, c.W, P, e->stream));
+                FB_HIP(hipEventRecord(ev1, e->stream));
+                FB_HIP(hipEventSynchronize(ev1));
+                float ms = 0.0f;
+                FB_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                fb_tune_entry t;
+                std::memset(&t, 0, sizeof t);
+                t.n = B.n;
+                t.mapping = c.map == MAP_SPL ? FB_MAP_SYSTEM_PER_LANE : FB_MAP_BODY_PER_LANE;
+                t.waves_per_group = c.W;
+                t.ms = ms;
+                entries.push_back(t);
+                if (ms < best) {
+                    best = ms;
+                    best_i = entries.size() - 1;
+                }
+            }
+            entries[best_i].chosen = 1;
+            const Plan cur = get_plan(B.n);
+            fb_status st = fb_set_plan(B.n, entries[best_i].mapping, entries[best_i].waves_per_group,
+                                       cur.groups_per_cu);
+            if (st != FB_OK)
+                return st;
+        }
+        // persistent launch: waves per group x groups per CU
+        const Plan keep0 = get_plan(0);
+        fb_opts po;
+        fb_opts_default(&po);
+        po.schedule = FB_SCHED_PERSISTENT;
+        double best = 1e300;
+        size_t best_i = 0;
+        for (int W : {1, 2, 4}) {
+            const int occ = persistent_max_groups_per_cu(0, W);
+            for (int g : {1, 2, 4, 8, 16, 32}) {
+                if (occ > 0 && g > occ)
+                    continue;
+                fb_status st = fb_set_plan(0, FB_MAP_AUTO, W, g);
+                if (st != FB_OK)
+                    return st;
+                FB_HIP(restore());
+                for (const Bucket &B : e->buckets)
+                    FB_HIP(launch_begin_run(B, 1, steps, 0.0, dt, 0, 0.0, e->stream));
+                FB_HIP(hipEventRecord(ev0, e->stream));
+                st = run_persistent(e, po, steps);
+                if (st != FB_OK)
+                    return st;
+                FB_HIP(hipEventRecord(ev1, e->stream));
+                FB_HIP(hipEventSynchronize(ev1));
+                float ms = 0.0f;
+                FB_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                fb_tune_entry t;
+                std::memset(&t, 0, sizeof t);
+                t.n = 0;
+                t.mapping = FB_MAP_AUTO;
+                t.waves_per_group = W;
+                t.groups_per_cu = g;
+                t.ms = ms;
+                entries.push_back(t);
+                if (ms < best) {
+                    best = ms;
+                    best_i = entries.size() - 1;
+                }
+            }
+        }
+        (void)keep0;
+        entries[best_i].chosen = 1;
+        fb_status st = fb_set_plan(0, FB_MAP_AUTO, entries[best_i].waves_per_group,
+                                   entries[best_i].groups_per_cu);
+        if (st != FB_OK)
+            return st;
+        FB_HIP(restore());
+        FB_HIP(hipStreamSynchronize(e->stream));
+        return FB_OK;
+    };
+    result = run();
+    (void)hipStreamSynchronize(e->stream);
+    if (ev0)
+        (void)hipEventDestroy(ev0);
+    if (ev1)
+        (void)hipEventDestroy(ev1);
+    (void)hipFree(backup);
+    if (out)
+        for (int32_t i = 0; i < max_out && i < (int32_t)entries.size(); ++i)
+            out[i] = entries[i];
+    if (n_out)
+        *n_out = (int32_t)entries.size();
+    return result;
 }
 
 fb_status fb_profile_enable(int32_t on)

@@ -1,0 +1,69 @@
+// Host-runtime internals shared by fb_runtime.cpp (ensembles, plans, timing)
+// and fb_server.cpp (continuous-batching server).  Not part of the ABI.
+#pragma once
+
+#include "fewbody.h"
+#include "fb_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace fb {
+namespace rt {
+
+// Record an error message for fb_last_error() and return `code`.
+fb_status fail(fb_status code, const char *fmt, ...);
+fb_status hip_fail(hipError_t e, const char *what);
+
+#define FB_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess)                         \
+            return ::fb::rt::hip_fail(e_, #call);     \
+    } while (0)
+
+struct Plan {
+    int mapping;          // MAP_SPL / MAP_BPL
+    int waves_per_group;  // 1..4
+    int groups_per_cu;    // persistent schedule only (entry 0)
+};
+Plan get_plan(int n);
+
+// Brackets the integration launches enqueued in its scope with HIP events on
+// `s` when the kernel timer is enabled.
+struct ProfScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit ProfScope(hipStream_t st);
+    ~ProfScope();
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Byte offsets of one body-count bucket inside an ensemble workspace.
+struct BucketLayout {
+    int n, count, pitch;
+    size_t st, t, t_end, dt, dtn, t0run, krun, nfull, steps, status, orig;
+};
+
+// Device workspace of one ensemble: buckets in descending body count, then
+// the tables, staging and scheduling arrays.
+struct Layout {
+    std::vector<BucketLayout> b;
+    int64_t n_bodies = 0;
+    int max_tiles = 0;
+    int list_total = 0;
+    size_t buckets, orig_off, staging, diag, ints, tiles, lists0, lists1, list_base, counts0,
+        counts1, order, mapping, total;
+};
+
+bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L);
+std::vector<Bucket> bucket_views(char *base, const Layout &L);
+// Caller's system index of every slot of bucket B (padding slots -> 0).
+std::vector<int> slot_origins(const std::vector<int32_t> &n_body, const Bucket &B);
+
+}  // namespace rt
+}  // namespace fb

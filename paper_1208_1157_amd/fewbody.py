@@ -38,6 +38,27 @@ class FbOpts(ctypes.Structure):
                 ("steps_per_quantum", ctypes.c_int32), ("compact", ctypes.c_int32)]
 
 
+class FbServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_resident", ctypes.c_int32),
+                ("steps_per_quantum", ctypes.c_int32)]
+
+
+class FbServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("resident", ctypes.c_int64), ("quanta", ctypes.c_int64),
+                ("system_steps", ctypes.c_double), ("busy_seconds", ctypes.c_double),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
+
+
+class FbTuneEntry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("mapping", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("ms", ctypes.c_double), ("chosen", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = range(5)
+
 _p = ctypes.c_void_p
 _i32, _i64, _d, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
@@ -56,8 +77,19 @@ _SIGS = {
     "fb_ensemble_destroy": (ctypes.c_int, [_p]),
     "fb_set_plan": (ctypes.c_int, [_i32, _i32, _i32, _i32]),
     "fb_get_plan": (ctypes.c_int, [_i32, _p, _p, _p]),
+    "fb_autotune": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbTuneEntry), _i32, ctypes.POINTER(_i32)]),
     "fb_profile_enable": (ctypes.c_int, [_i32]),
     "fb_profile_read": (ctypes.c_int, [_p, _p]),
+    "fb_server_opts_default": (None, [ctypes.POINTER(FbServerOpts)]),
+    "fb_server_create": (ctypes.c_int, [ctypes.POINTER(FbServerOpts), _p, ctypes.POINTER(_p)]),
+    "fb_server_submit": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p, _d, _d, ctypes.POINTER(_i64)]),
+    "fb_server_poll": (ctypes.c_int, [_p, _i64, ctypes.POINTER(_i32)]),
+    "fb_server_wait": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(_i32)]),
+    "fb_server_result": (ctypes.c_int, [_p, _i64, _p, _p, _p, _p, _p, _p]),
+    "fb_server_cancel": (ctypes.c_int, [_p, _i64]),
+    "fb_server_get_stats": (ctypes.c_int, [_p, ctypes.POINTER(FbServerStats)]),
+    "fb_server_destroy": (ctypes.c_int, [_p]),
+    "fb_monotonic_seconds": (_d, []),
     "fb_last_error": (ctypes.c_char_p, []),
     "fb_version": (ctypes.c_char_p, []),
 }
@@ -206,6 +238,15 @@ class Ensemble:
     def synchronize(self):
         _check(_lib.fb_synchronize(self._handle))
 
+    def autotune(self, steps, dt):
+        """Time the candidate plans on this ensemble and install the fastest
+        (state restored afterwards).  Returns every timed candidate."""
+        buf = (FbTuneEntry * 512)()
+        n = ctypes.c_int32()
+        _check(_lib.fb_autotune(self._handle, int(steps), float(dt), buf, 512, ctypes.byref(n)))
+        return [{k: getattr(buf[i], k) for k, _ in FbTuneEntry._fields_ if k != "pad"}
+                for i in range(min(n.value, 512))]
+
     # -- read back -----------------------------------------------------------
     def state(self):
         N, S = self.n_bodies, self.n_sys
@@ -233,6 +274,88 @@ class Ensemble:
             _check(_lib.fb_ensemble_destroy(self._handle))
             self._handle = ctypes.c_void_p()
             self._workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def monotonic() -> float:
+    """The library's monotonic clock (CLOCK_MONOTONIC seconds, as time.monotonic())."""
+    return _lib.fb_monotonic_seconds()
+
+
+class Server:
+    """Continuous-batching integration server (fb_server_*).
+
+    submit() queues an ensemble with its own t_end and fixed dt and returns
+    at once; a native worker thread admits requests by device-memory budget
+    and resident cap, advances every resident system in fused quanta, and
+    retires finished requests."""
+
+    def __init__(self, budget_bytes=0, max_resident=0, steps_per_quantum=0, stream=None):
+        o = FbServerOpts(int(budget_bytes), int(max_resident), int(steps_per_quantum))
+        self._h = ctypes.c_void_p()
+        sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(_lib.fb_server_create(ctypes.byref(o), sp, ctypes.byref(self._h)))
+        self._shapes = {}
+
+    def submit(self, n_body, mass, pos, vel, t_end, dt) -> int:
+        nb = np.ascontiguousarray(n_body, dtype=np.int32)
+        m = np.ascontiguousarray(mass, dtype=np.float64)
+        x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        v = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        rid = ctypes.c_int64()
+        _check(_lib.fb_server_submit(self._h, int(nb.shape[0]), _ptr(nb), _ptr(m), _ptr(x), _ptr(v),
+                                     float(t_end), float(dt), ctypes.byref(rid)))
+        self._shapes[rid.value] = (int(nb.shape[0]), int(m.shape[0]))
+        return rid.value
+
+    def submit_gen(self, ens, t_end, dt) -> int:
+        return self.submit(ens.n_body, ens.mass, ens.pos, ens.vel, t_end, dt)
+
+    def poll(self, rid) -> int:
+        st = ctypes.c_int32()
+        _check(_lib.fb_server_poll(self._h, int(rid), ctypes.byref(st)))
+        return st.value
+
+    def wait(self, rid, timeout=-1.0) -> int:
+        st = ctypes.c_int32()
+        _check(_lib.fb_server_wait(self._h, int(rid), float(timeout), ctypes.byref(st)))
+        return st.value
+
+    def result(self, rid):
+        S, N = self._shapes.pop(rid)
+        pos, vel = np.empty((N, 3)), np.empty((N, 3))
+        t = np.empty(S)
+        status = np.empty(S, dtype=np.int32)
+        steps = np.empty(S, dtype=np.int64)
+        times = np.empty(3)
+        _check(_lib.fb_server_result(self._h, int(rid), _ptr(pos), _ptr(vel), _ptr(t), _ptr(status),
+                                     _ptr(steps), _ptr(times)))
+        return {"pos": pos, "vel": vel, "t": t, "status": status, "steps": steps,
+                "t_submit": times[0], "t_admit": times[1], "t_done": times[2]}
+
+    def cancel(self, rid):
+        _check(_lib.fb_server_cancel(self._h, int(rid)))
+
+    def stats(self) -> dict:
+        st = FbServerStats()
+        _check(_lib.fb_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in FbServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_lib.fb_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -1,0 +1,114 @@
+"""Continuous-batching server on the GPU: results alone vs in the mix,
+admission by memory budget, cancellation, and a short Poisson trace."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_1157_amd import gen, serve
+from tests.helpers import assert_parity, threads
+
+pytestmark = pytest.mark.gpu
+H = 2 * math.pi / 1000
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def small_requests(n_req, seed, max_sys=48, orbits=(0.3, 2.5)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_req):
+        ens = gen.ragged_hill(int(rng.integers(1, max_sys + 1)), seed=int(rng.integers(1 << 30)),
+                              n_lo=3, n_hi=10)
+        out.append((ens, 2 * math.pi * rng.uniform(*orbits)))
+    return out
+
+
+def test_results_identical_alone_and_in_the_mix(fb, ora):
+    reqs = small_requests(16, seed=1)
+    say("mix of", len(reqs), "requests")
+    with fb.Server(steps_per_quantum=300) as srv:
+        ids = [srv.submit_gen(e, t, H) for e, t in reqs]
+        mixed = []
+        for rid in ids:
+            assert srv.wait(rid, 120.0) == fb.REQ_DONE
+            mixed.append(srv.result(rid))
+        # continuous batching: later requests were admitted before earlier ones finished
+        assert any(mixed[j]["t_admit"] < mixed[i]["t_done"] for i in range(len(mixed))
+                   for j in range(i + 1, len(mixed)))
+    for k, (ens, t_end) in enumerate(reqs):
+        with fb.Server(steps_per_quantum=300) as solo:
+            rid = solo.submit_gen(ens, t_end, H)
+            solo.wait(rid, 60.0)
+            alone = solo.result(rid)
+        assert np.array_equal(alone["pos"], mixed[k]["pos"]), k
+        assert np.array_equal(alone["vel"], mixed[k]["vel"]), k
+        assert np.all(mixed[k]["t"] == t_end) and np.all(mixed[k]["status"] == fb.DONE)
+        assert np.all(mixed[k]["steps"] == serve.request_steps(t_end, H))
+        # the same integration through an ensemble
+        E = fb.from_gen(ens)
+        E.integrate(t_end, H, fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=300))
+        st = E.state()
+        E.close()
+        assert np.array_equal(st["pos"], mixed[k]["pos"]), k
+    # and against the oracle: whole steps then the shortened step
+    for k, (ens, t_end) in enumerate(reqs[:4]):
+        nfull = int(math.floor(t_end / H))
+        X, V, A, J = ora.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, H, nfull, nthreads=threads())
+        off = ens.offsets
+        for s in range(ens.n_sys):
+            sl = slice(off[s], off[s + 1])
+            X[sl], V[sl], _, _ = ora.integrate_fixed(ens.mass[sl], X[sl], V[sl], t_end - nfull * H, 1,
+                                                     acc=A[sl], jerk=J[sl])
+        assert_parity(ens.n_body, mixed[k]["pos"], mixed[k]["vel"], X, V, label="serving vs oracle")
+
+
+def test_admission_by_memory_budget(fb):
+    reqs = small_requests(6, seed=2, max_sys=64, orbits=(1.0, 1.5))
+    need = max(fb.workspace_bytes(e.n_body) for e, _ in reqs)
+    budget = int(2.2 * need)
+    say("budget", budget)
+    with fb.Server(budget_bytes=budget, steps_per_quantum=200) as srv:
+        ids = [srv.submit_gen(e, t, H) for e, t in reqs]
+        res = []
+        for rid in ids:
+            assert srv.wait(rid, 120.0) == fb.REQ_DONE
+            res.append(srv.result(rid))
+        st = srv.stats()
+        assert st["peak_bytes"] <= budget
+        assert st["completed"] == len(reqs)
+    # someone had to wait for memory: admitted after another finished
+    assert any(res[j]["t_admit"] >= res[i]["t_done"] for i in range(len(res)) for j in range(len(res)) if i != j)
+    with fb.Server(budget_bytes=16384) as tiny:
+        with pytest.raises(fb.FewbodyError) as ei:
+            tiny.submit_gen(reqs[0][0], 1.0, H)
+        assert ei.value.code == fb.E_BUDGET
+
+
+def test_cancel_and_errors(fb):
+    ens = gen.ragged_hill(8, seed=3, n_lo=3, n_hi=6)
+    with fb.Server(steps_per_quantum=100) as srv:
+        rid = srv.submit_gen(ens, 2 * math.pi * 200, H)
+        srv.cancel(rid)
+        assert srv.wait(rid, 60.0) == fb.REQ_CANCELLED
+        with pytest.raises(fb.FewbodyError) as ei:
+            srv.result(rid)
+        assert ei.value.code == fb.E_STATE
+        with pytest.raises(fb.FewbodyError) as ei:
+            srv.poll(10 ** 9)
+        assert ei.value.code == fb.E_NOTFOUND
+
+
+def test_short_poisson_trace(fb):
+    trace = gen.serving_trace(60, rate=200.0, seed=5, max_sys=256)
+    for r in trace:
+        r.t_end = min(r.t_end, 2 * math.pi * 20)
+    say("poisson trace", len(trace))
+    rep = serve.run_trace(fb, trace, steps_per_quantum=1000)
+    say({k: v for k, v in rep.items()})
+    assert rep["requests"] == 60
+    assert 0 < rep["p50_latency_s"] <= rep["p99_latency_s"] < 120
+    assert rep["aggregate_system_steps_per_s"] > 0
