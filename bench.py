@@ -38,7 +38,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 # HBM bytes per launch of the integration kernel on this workload, from the
 # FETCH_SIZE / WRITE_SIZE counter passes (scaled by a 256 MiB copy kernel's
 # reading) recorded in profiles/, keyed by the kernel source they measured.
-MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0}
+MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1}
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 
 
@@ -145,10 +145,12 @@ def lifetimes_extras(fb, gen, torch, log, orbits=100.0, quantum=2000):
     return out
 
 
-def serving_report(fb, gen, log, n_req=2000):
+def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000):
     from paper_1208_1157_amd import serve
     trace = gen.serving_trace(n_req, rate=200.0, seed=4)
-    rep = serve.run_trace(fb, trace, log=log)
+    rep = serve.run_trace(fb, trace, max_resident=max_resident, steps_per_quantum=quantum, log=log)
+    rep["max_resident"] = max_resident
+    rep["steps_per_quantum"] = quantum
     rep["workload"] = (f"serving: {n_req} requests, Poisson 200 req/s, 1..4096 systems (log-uniform) of 3..10 "
                        f"bodies, t_end 2pi*10^U(1,3), dt 2pi/1000")
     return rep
@@ -167,6 +169,8 @@ def main():
                          "(plain vs compaction) comparisons")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-max-resident", type=int, default=4096)
+    ap.add_argument("--serve-quantum", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -255,7 +259,7 @@ def main():
 
     extras = {}
     if not args.no_serve:
-        rep = serving_report(fb, gen, log, args.serve_requests)
+        rep = serving_report(fb, gen, log, args.serve_requests, args.serve_max_resident, args.serve_quantum)
         result["p50_latency_s"] = rep["p50_latency_s"]
         result["p99_latency_s"] = rep["p99_latency_s"]
         extras["serving"] = rep

@@ -92,9 +92,13 @@ typedef struct {
                                    dt = eta * min over pairs |a_ij|/|j_ij| of
                                    the pair's two-body relative acceleration and
                                    jerk at the step's last evaluation (the
-                                   set-up evaluation for the first step); the
-                                   final step is shortened to land on t_end.    */
-    double eta;                 /* adaptive accuracy parameter                  */
+                                   set-up evaluation for the first step).
+                                   2: Eq. 5's rule, dt = eta [sum_i |j_i|^2 /
+                                   |a_i|^2]^(-1/2) from the accelerations and
+                                   jerks that start the step (eta is tau).
+                                   Either way the final step is shortened to
+                                   land on t_end.                               */
+    double eta;                 /* adaptive accuracy parameter (tau for rule 2) */
     int32_t stop_rules;         /* FB_STOP_* bits, checked after every step     */
     double r_eject;             /* ejection radius from the star                */
     int64_t max_steps;          /* per-system cap on steps (<=0: unlimited)     */
@@ -242,7 +246,7 @@ enum { FB_REQ_QUEUED = 0, FB_REQ_RUNNING = 1, FB_REQ_DONE = 2, FB_REQ_CANCELLED 
 typedef struct {
     size_t budget_bytes;        /* device memory for resident requests, allocated
                                    once at creation (0: 4 GiB)                      */
-    int32_t max_resident;       /* requests resident at once (0: 256)               */
+    int32_t max_resident;       /* requests resident at once (0: 4096)              */
     int32_t steps_per_quantum;  /* steps per resident system per quantum (0: 2000)  */
 } fb_server_opts;
 

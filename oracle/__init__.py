@@ -53,6 +53,8 @@ def lib():
         L.ora_energy.argtypes = [i, p, p, p, p, p]
         L.ora_pair_timestep.argtypes = [i, p, p, p, d]
         L.ora_pair_timestep.restype = d
+        L.ora_paper_timestep.argtypes = [i, p, p, d]
+        L.ora_paper_timestep.restype = d
         L.ora_check_stop.argtypes = [i, p, p, p, i, d]
         L.ora_check_stop.restype = i
         L.ora_integrate_adaptive.argtypes = [i, p, p, p, p, p, p, d, d, i, d, l, p, p, i]
@@ -150,10 +152,18 @@ def check_stop(mass, pos, vel, stop_rules=3, r_eject=100.0):
                                 int(stop_rules), float(r_eject))
 
 
+def paper_timestep(acc, jerk, tau):
+    """Eq. 5: tau [sum_i |j_i|^2/|a_i|^2]^(-1/2)."""
+    a = _f64(acc).reshape(-1, 3)
+    j = _f64(jerk).reshape(-1, 3)
+    return lib().ora_paper_timestep(a.shape[0], _p(a), _p(j), float(tau))
+
+
 def integrate_adaptive(mass, pos, vel, t_end, eta=0.01, stop_rules=3, r_eject=100.0,
-                       max_steps=10**9, t0=0.0):
+                       max_steps=10**9, t0=0.0, paper_rule=False):
     """Adaptive integration of one system to t_end or a stop rule.
 
+    paper_rule selects Eq. 5 (eta is tau) instead of the pairwise rule.
     Returns dict(pos, vel, acc, jerk, t, dt_next, steps, status)."""
     m = _f64(mass)
     n = m.shape[0]
@@ -164,7 +174,7 @@ def integrate_adaptive(mass, pos, vel, t_end, eta=0.01, stop_rules=3, r_eject=10
     steps = np.zeros(1, dtype=np.int64)
     st = lib().ora_integrate_adaptive(n, _p(m), _p(x), _p(v), _p(a), _p(j), _p(t), float(t_end),
                                       float(eta), int(stop_rules), float(r_eject), int(max_steps),
-                                      _p(dtn), _p(steps), 1)
+                                      _p(dtn), _p(steps), 1 | (2 if paper_rule else 0))
     return {"pos": x, "vel": v, "acc": a, "jerk": j, "t": float(t[0]), "dt_next": float(dtn[0]),
             "steps": int(steps[0]), "status": int(st)}
 

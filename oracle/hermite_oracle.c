@@ -233,6 +233,20 @@ double ora_pair_timestep(int n, const double *m, const double *x,
     return eta * best;
 }
 
+/* Eq. 5 (Section 4.3.1): dt = tau [sum_i |j_i|^2 / |a_i|^2]^(-1/2) over the
+ * bodies, from the acceleration and jerk at the beginning of the step. */
+double ora_paper_timestep(int n, const double *a0, const double *j0, double tau)
+{
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double *a = a0 + 3 * i, *j = j0 + 3 * i;
+        double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+        double jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+        sum = sum + jj / aa;
+    }
+    return tau / sqrt(sum);
+}
+
 /* Status after a committed step, from the stop rules.  stop_rules bit 0
  * enables the close-encounter test, bit 1 the ejection test. */
 int ora_check_stop(int n, const double *m, const double *x, const double *v,
@@ -275,6 +289,9 @@ int ora_check_stop(int n, const double *m, const double *x, const double *v,
  * one).  A step that would pass t_end is shortened to end on it and sets t
  * to t_end exactly.  A proposed step below 1e-12 |t_end| stalls the system.
  * flags bit 0: set-up evaluation of (a0, j0) and *dt_next first.
+ * flags bit 1: Eq. 5's rule (eta is tau; dt from the step's starting a0, j0,
+ * which are the previous step's last evaluation) instead of the pairwise
+ * rule.
  * Returns the final status. */
 int ora_integrate_adaptive(int n, const double *m, double *x, double *v,
                            double *a0, double *j0, double *t, double t_end,
@@ -284,9 +301,11 @@ int ora_integrate_adaptive(int n, const double *m, double *x, double *v,
 {
     if (n < 2 || n > ORA_MAX_BODIES)
         return -1;
+    const int paper_rule = (flags & 2) != 0;
     if (flags & 1) {
         ora_accjerk(n, m, x, v, a0, j0);
-        *dt_next = ora_pair_timestep(n, m, x, v, eta);
+        *dt_next = paper_rule ? ora_paper_timestep(n, a0, j0, eta)
+                              : ora_pair_timestep(n, m, x, v, eta);
     }
     double xp[3 * ORA_MAX_BODIES], vp[3 * ORA_MAX_BODIES];
     double xc[3 * ORA_MAX_BODIES], vc[3 * ORA_MAX_BODIES];
@@ -317,11 +336,13 @@ int ora_integrate_adaptive(int n, const double *m, double *x, double *v,
         memcpy(vc, vp, sizeof(double) * 3 * n);
         double dt_prop = 0.0;
         for (int it = 0; it < 2; ++it) {
-            if (it == 1)
+            if (it == 1 && !paper_rule)
                 dt_prop = ora_pair_timestep(n, m, xc, vc, eta);
             ora_accjerk(n, m, xc, vc, ak, jk);
             ora_correct(n, h, xp, vp, a0, j0, ak, jk, xc, vc);
         }
+        if (paper_rule)
+            dt_prop = ora_paper_timestep(n, ak, jk, eta);
         memcpy(x, xc, sizeof(double) * 3 * n);
         memcpy(v, vc, sizeof(double) * 3 * n);
         memcpy(a0, ak, sizeof(double) * 3 * n);

@@ -94,3 +94,65 @@ def tune(fb, ens, dt, target_ms=20.0, cache_path=DEFAULT_CACHE, use_cache=True, 
         log(f"[autotune] {len(entries)} candidates in {time.perf_counter() - t0:.1f} s, {steps} steps each")
     return {"plans": plans, "entries": entries, "seconds": time.perf_counter() - t0, "cached": False,
             "calibration_steps": steps}
+
+
+def sweep(fb, gen, n_lo=3, n_hi=16, per_n=8192, steps=None, seed=21, log=print):
+    """Per-body-count throughput of every candidate plan (no cache): an
+    ensemble with `per_n` systems of each body count n_lo..n_hi (the
+    ragged_hill distribution), timed by fb_autotune.  Returns rows of
+    (n, mapping, waves_per_group, groups_per_cu, ms, algorithmic TFLOP/s,
+    system-steps/s, chosen)."""
+    import numpy as np
+    parts = [gen.ragged_hill(per_n, seed=seed + n, n_lo=n, n_hi=n) for n in range(n_lo, n_hi + 1)]
+    nb = np.concatenate([p.n_body for p in parts])
+    ens = gen.Ensemble(nb, np.concatenate([p.mass for p in parts]), np.concatenate([p.pos for p in parts]),
+                       np.concatenate([p.vel for p in parts]))
+    dt = 2 * np.pi / 2000
+    E = fb.from_gen(ens)
+    try:
+        if steps is None:
+            E.integrate_steps(8, dt)
+            E.synchronize()
+            t0 = time.perf_counter()
+            E.integrate_steps(32, dt)
+            E.synchronize()
+            per_step = (time.perf_counter() - t0) / 32
+            steps = int(min(max(0.3 / per_step, 64), 20000))
+        entries = E.autotune(steps, dt)
+    finally:
+        E.close()
+    rows = []
+    total_flops = float(sum(116.0 * n * (n - 1) / 2 + 120.0 * n for n in nb)) * steps
+    for e in entries:
+        n = e["n"]
+        if n > 0:
+            flops = per_n * (116.0 * n * (n - 1) / 2 + 120.0 * n) * steps
+            sys_steps = per_n * steps
+        else:
+            flops, sys_steps = total_flops, len(nb) * steps
+        s = e["ms"] / 1e3
+        rows.append((n, e["mapping"], e["waves_per_group"], e["groups_per_cu"], e["ms"],
+                     flops / s / 1e12, sys_steps / s, e["chosen"]))
+    return rows, steps
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_1208_1157_amd import fewbody as fb_mod
+    from paper_1208_1157_amd import gen as gen_mod
+    ap = argparse.ArgumentParser(description="per-body-count plan sweep (prints a markdown table)")
+    ap.add_argument("--per-n", type=int, default=8192)
+    ap.add_argument("--n-lo", type=int, default=3)
+    ap.add_argument("--n-hi", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=None)
+    a = ap.parse_args()
+    rows, steps = sweep(fb_mod, gen_mod, a.n_lo, a.n_hi, a.per_n, a.steps)
+    names = {0: "auto", 1: "system/lane", 2: "body/lane"}
+    print(f"plan sweep: {a.per_n} systems per body count, {steps} fixed steps of 2pi/2000 per candidate")
+    print("| n | mapping | waves/group | groups/CU | ms | algorithmic TFLOP/s | system-steps/s | chosen |")
+    print("|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        n = "all (persistent)" if r[0] == 0 else str(r[0])
+        print(f"| {n} | {names.get(r[1], r[1])} | {r[2]} | {r[3]} | {r[4]:.2f} | {r[5]:.2f} | {r[6]:.3e} | {'*' if r[7] else ''} |")

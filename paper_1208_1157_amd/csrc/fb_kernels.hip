@@ -384,6 +384,22 @@ __device__ __forceinline__ int spl_stop_flags(const double (&m)[N], const double
     return fl;
 }
 
+// Eq. 5 (Section 4.3.1): tau [sum_i |j_i|^2 / |a_i|^2]^(-1/2) from the
+// accelerations and jerks that start the next step, summed in body order.
+template <int N>
+__device__ __forceinline__ double paper_dt(const double (&a)[N][3], const double (&jk)[N][3],
+                                           double tau)
+{
+    double sum = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        const double aa = fma(a[b][2], a[b][2], fma(a[b][1], a[b][1], a[b][0] * a[b][0]));
+        const double jj = fma(jk[b][2], jk[b][2], fma(jk[b][1], jk[b][1], jk[b][0] * jk[b][0]));
+        sum += jj / aa;
+    }
+    return tau * rsqrt_nr(sum);
+}
+
 // Integrate one system (one lane) for at most P.quantum steps.
 template <int N, bool ADV>
 __device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
@@ -437,7 +453,9 @@ __device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
         if (!plan_step(c, P, h, last))
             break;
         const double w = spl_step<N, ADV>(m, x, v, a, jk, make_coef(h));
-        const double dtp = ADV ? P.eta * rsqrt_nr(w) : 0.0;
+        double dtp = 0.0;
+        if (ADV)
+            dtp = P.adaptive == 2 ? paper_dt<N>(a, jk, P.eta) : P.eta * rsqrt_nr(w);
         finish_step(c, P, last, h, dtp);
         if (ADV) {
             const int fl = spl_stop_flags<N>(m, x, v, P);
@@ -492,24 +510,48 @@ __device__ __forceinline__ BplLds &wave_lds()
     return fb_dyn_lds[threadIdx.x >> 6];
 }
 
-// k-th interaction partner of body b (0 <= k < n-1): the other planets in
-// ascending order, then the star (the star itself sums planets 1..n-1).
-template <int N>
-__device__ __forceinline__ int partner(const int k, const int b)
-{
-    if (b == 0)
-        return k + 1;
-    if (k == N - 2)
-        return 0;
-    return k + 1 + (k + 1 >= b ? 1 : 0);
-}
-
 // k-th planet partner of planet b (0 <= k < n-2).
 __device__ __forceinline__ int planet_partner(const int k, const int b)
 {
     return k + 1 + (k + 1 >= b ? 1 : 0);
 }
 
+// One interaction of body i (this lane) with the partner stored at LDS index
+// idx: adds m_j A and m_j J (Eq. 1 and its time derivative).
+template <bool TS>
+__device__ __forceinline__ void bpl_interact(const BplLds &L, const int idx,
+                                             const double (&xi)[3], const double (&vi)[3],
+                                             double (&a)[3], double (&jk)[3], double &wmax)
+{
+    const double2 p0 = L.xy[idx];
+    const double2 p1 = L.zvx[idx];
+    const double2 p2 = L.vyvz[idx];
+    const double mj = L.m[idx];
+    const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
+    const double ux = p1.y - vi[0], uy = p2.x - vi[1], uz = p2.y - vi[2];
+    const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+    const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
+    const double ri = rsqrt_nr(r2);
+    const double ri2 = ri * ri;
+    const double mr3 = mj * (ri2 * ri);
+    const double al = 3.0 * ru * ri2;
+    a[0] = fma(mr3, rx, a[0]);
+    a[1] = fma(mr3, ry, a[1]);
+    a[2] = fma(mr3, rz, a[2]);
+    jk[0] = fma(mr3, fma(-al, rx, ux), jk[0]);
+    jk[1] = fma(mr3, fma(-al, ry, uy), jk[1]);
+    jk[2] = fma(mr3, fma(-al, rz, uz), jk[2]);
+    if (TS) {
+        const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+        wmax = fmax(wmax, fma(al, ru, u2) * ri2);
+    }
+}
+
+// Accelerations and jerks of this lane's body from all n-1 partners read
+// from the wavefront's LDS slice.  Partner order: the other planets in
+// ascending order, then the star (the star lane sums planets 1..n-1), so the
+// star's contribution is added last.  Branch-free: the n-2 planet partners
+// skip this lane's own index arithmetically and the last partner is peeled.
 template <int N, bool TS>
 __device__ __forceinline__ void bpl_eval(BplLds &L, const int lane, const int b, const int s,
                                          const double (&xi)[3], const double (&vi)[3],
@@ -525,32 +567,13 @@ __device__ __forceinline__ void bpl_eval(BplLds &L, const int lane, const int b,
         a[c] = 0.0;
         jk[c] = 0.0;
     }
+    const int skip = b == 0 ? (1 << 20) : b;
 #pragma unroll FB_BPL_UNROLL
-    for (int k = 0; k < N - 1; ++k) {
-        const int idx = partner<N>(k, b) * S + s;
-        const double2 p0 = L.xy[idx];
-        const double2 p1 = L.zvx[idx];
-        const double2 p2 = L.vyvz[idx];
-        const double mj = L.m[idx];
-        const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
-        const double ux = p1.y - vi[0], uy = p2.x - vi[1], uz = p2.y - vi[2];
-        const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
-        const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
-        const double ri = rsqrt_nr(r2);
-        const double ri2 = ri * ri;
-        const double mr3 = mj * (ri2 * ri);
-        const double al = 3.0 * ru * ri2;
-        a[0] = fma(mr3, rx, a[0]);
-        a[1] = fma(mr3, ry, a[1]);
-        a[2] = fma(mr3, rz, a[2]);
-        jk[0] = fma(mr3, fma(-al, rx, ux), jk[0]);
-        jk[1] = fma(mr3, fma(-al, ry, uy), jk[1]);
-        jk[2] = fma(mr3, fma(-al, rz, uz), jk[2]);
-        if (TS) {
-            const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
-            wmax = fmax(wmax, fma(al, ru, u2) * ri2);
-        }
+    for (int k = 0; k < N - 2; ++k) {
+        const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
+        bpl_interact<TS>(L, j * S + s, xi, vi, a, jk, wmax);
     }
+    bpl_interact<TS>(L, (b == 0 ? N - 1 : 0) * S + s, xi, vi, a, jk, wmax);
     wave_sync();
 }
 
@@ -564,6 +587,21 @@ __device__ __forceinline__ double sys_max(BplLds &L, int lane, int s, double v)
 #pragma unroll
     for (int k = 1; k < N; ++k)
         r = fmax(r, L.red[k * S + s]);
+    wave_sync();
+    return r;
+}
+
+// Sum over the system's lanes in body order (deterministic).
+template <int N>
+__device__ __forceinline__ double sys_sum(BplLds &L, int lane, int s, double v)
+{
+    constexpr int S = 64 / N;
+    L.red[lane] = v;
+    wave_sync();
+    double r = L.red[s];
+#pragma unroll
+    for (int k = 1; k < N; ++k)
+        r += L.red[k * S + s];
     wave_sync();
     return r;
 }
@@ -678,8 +716,13 @@ __device__ bool bpl_run(const Bucket &B, const int first, const int count, const
         for (int cc = 0; cc < 3; ++cc)
             correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
         double dtp = 0.0;
-        if (ADV && P.adaptive)
+        if (ADV && P.adaptive == 1)
             dtp = P.eta * rsqrt_nr(sys_max<N>(L, lane, s, w));
+        if (ADV && P.adaptive == 2) {
+            const double aa = fma(ak[2], ak[2], fma(ak[1], ak[1], ak[0] * ak[0]));
+            const double jj = fma(jk[2], jk[2], fma(jk[1], jk[1], jk[0] * jk[0]));
+            dtp = P.eta * rsqrt_nr(sys_sum<N>(L, lane, s, jj / aa));
+        }
         if (act) {
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
@@ -998,12 +1041,27 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
         B.nfull[s] = 0;
         B.dt[s] = 0.0;
         B.status[s] = t < t_end ? ST_ACTIVE : ST_DONE;
-        if (!(B.dtn[s] > 0.0)) {
+        // Eq. 5's step depends only on the stored (a0, j0), so it is always
+        // recomputed (identical to the carried value); the pairwise rule's
+        // carried step comes from the last evaluation's state and is kept.
+        if (adaptive == 2 || !(B.dtn[s] > 0.0)) {
             double m[N], x[N][3], v[N][3], a[N][3], jk[N][3];
             load_xv<N>(B, s, m, x, v);
-            double w = 0.0;
-            spl_accjerk<N, true>(m, x, v, a, jk, w);
-            B.dtn[s] = eta * rsqrt_nr(w);
+            if (adaptive == 2) {
+                const size_t pitch = B.pitch;
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        a[b][c] = B.st[((R_A + c) * N + b) * pitch + s];
+                        jk[b][c] = B.st[((R_J + c) * N + b) * pitch + s];
+                    }
+                B.dtn[s] = paper_dt<N>(a, jk, eta);
+            } else {
+                double w = 0.0;
+                spl_accjerk<N, true>(m, x, v, a, jk, w);
+                B.dtn[s] = eta * rsqrt_nr(w);
+            }
         }
         return;
     }

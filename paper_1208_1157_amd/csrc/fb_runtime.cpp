@@ -365,7 +365,7 @@ bool finite_all(const double *p, size_t n)
 StepParams make_params(const fb_opts &o, int quantum)
 {
     StepParams P;
-    P.adaptive = o.adaptive ? 1 : 0;
+    P.adaptive = o.adaptive == 2 ? 2 : (o.adaptive ? 1 : 0);
     P.stop_rules = o.stop_rules & (FB_STOP_ENCOUNTER | FB_STOP_EJECT);
     P.eta = o.eta;
     P.r_eject = o.r_eject;
@@ -377,6 +377,8 @@ StepParams make_params(const fb_opts &o, int quantum)
 
 fb_status check_opts(const fb_opts &o)
 {
+    if (o.adaptive < 0 || o.adaptive > 2)
+        return fail(FB_E_INVAL, "adaptive must be 0 (fixed), 1 (pairwise rule) or 2 (Eq. 5 rule)");
     if (o.adaptive && !(std::isfinite(o.eta) && o.eta > 0.0))
         return fail(FB_E_INVAL, "eta must be finite and > 0");
     if ((o.stop_rules & FB_STOP_EJECT) && !(o.r_eject > 0.0))
@@ -739,7 +741,8 @@ fb_status fb_integrate(fb_ensemble *e, double t_end, double dt, const fb_opts *p
     if (e->n_sys == 0)
         return FB_OK;
     for (const Bucket &B : e->buckets)
-        FB_HIP(launch_begin_run(B, 0, 0, t_end, dt, o.adaptive ? 1 : 0, o.eta, e->stream));
+        FB_HIP(launch_begin_run(B, 0, 0, t_end, dt, o.adaptive == 2 ? 2 : (o.adaptive ? 1 : 0),
+                                o.eta, e->stream));
     return run(e, o, -1);
 }
 

@@ -447,7 +447,7 @@ void fb_server_opts_default(fb_server_opts *o)
         return;
     std::memset(o, 0, sizeof *o);
     o->budget_bytes = (size_t)4 << 30;
-    o->max_resident = 256;
+    o->max_resident = 4096;
     o->steps_per_quantum = 2000;
 }
 

@@ -13,6 +13,12 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+# torch first: its wheel carries its own HIP runtime (SONAME libamdhip64.so.7,
+# which torch's libraries request as libamdhip64.so).  Loading torch before
+# this library makes the dynamic loader resolve our libamdhip64.so.7 to that
+# same runtime, so the process has exactly one HIP runtime and torch's device
+# memory and streams are valid in our calls.
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfewbody.so")

@@ -302,3 +302,34 @@ def test_adaptive_decisions_agree_long_horizon(plans, ora):
                 for s, o in enumerate(outs))
     say("status agree", same, "steps within 1%", close, "of", ens.n_sys)
     assert same >= 0.95 * ens.n_sys and close >= 0.9 * ens.n_sys
+
+
+@pytest.mark.parametrize("mapping", ["spl", "bpl"])
+def test_paper_step_rule_parity(plans, ora, mapping):
+    """Eq. 5's step rule (adaptive = 2, eta = tau = 1.7e-2 as in Section 5.2.2)
+    on Section 5.1's initial conditions (n = 3..6) and a ragged Hill-spaced
+    mix, 5 inner orbits: same step counts as the oracle and parity to 1e-10."""
+    fb = plans
+    for n in range(2, 17):
+        use_spl = mapping == "spl" and n <= 6
+        fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
+    parts = [gen.paper_ics(4, n) for n in (3, 4, 5, 6)] + [gen.ragged_hill(40, seed=8, n_lo=3, n_hi=12)]
+    nb = np.concatenate([p.n_body for p in parts])
+    ens = gen.Ensemble(nb, np.concatenate([p.mass for p in parts]), np.concatenate([p.pos for p in parts]),
+                       np.concatenate([p.vel for p in parts]))
+    t_end = 2 * math.pi * 5
+    say("Eq.5 rule", mapping, ens.n_sys)
+    E = fb.from_gen(ens)
+    E.integrate(t_end, 0.0, fb.Opts(adaptive=2, eta=1.7e-2))
+    st = E.state()
+    E.close()
+    off = ens.offsets
+    for s in range(ens.n_sys):
+        o = ora.integrate_adaptive(*ens.system(s), t_end=t_end, eta=1.7e-2, stop_rules=0, paper_rule=True)
+        assert o["status"] == st["status"][s] == fb.DONE
+        assert o["steps"] == st["steps"][s], (s, o["steps"], st["steps"][s])
+        sl = slice(off[s], off[s + 1])
+        ex = per_system_rel_err([ens.n_body[s]], st["pos"][sl], o["pos"])[0]
+        ev = per_system_rel_err([ens.n_body[s]], st["vel"][sl], o["vel"])[0]
+        assert ex <= REL_TOL and ev <= REL_TOL, (s, ex, ev)
+        assert st["t"][s] == t_end

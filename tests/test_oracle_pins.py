@@ -493,3 +493,28 @@ def test_ensemble_driver_equals_single_system_calls(ora):
         sl = slice(off[s], off[s + 1])
         assert np.array_equal(X[sl], xs) and np.array_equal(V[sl], vs)
         assert np.array_equal(A[sl], as_) and np.array_equal(J[sl], js)
+
+
+def test_paper_timestep_closed_form(ora):
+    """Eq. 5 on a circular two-body orbit: |j_i|/|a_i| equals the orbital
+    angular velocity w for both bodies, so dt = tau / (sqrt(2) w)."""
+    m0, m1, a = 1.0, 3e-3, 1.3
+    x, v = kepler.two_body_state(m0, m1, a, 0.0, 0.37)
+    acc, jerk = ora.accjerk(np.array([m0, m1]), x, v)
+    w = math.sqrt((m0 + m1) / a ** 3)
+    tau = 1.7e-2
+    assert abs(ora.paper_timestep(acc, jerk, tau) - tau / (math.sqrt(2.0) * w)) < 1e-14
+    # three bodies: the sum runs over every body
+    acc3 = np.array([[1.0, 0, 0], [0, 2.0, 0], [0, 0, 4.0]])
+    jerk3 = np.array([[0, 3.0, 0], [2.0, 0, 0], [0, 4.0, 0]])
+    assert abs(ora.paper_timestep(acc3, jerk3, 0.5) - 0.5 / math.sqrt(9.0 + 1.0 + 1.0)) < 1e-15
+
+
+def test_paper_rule_adaptive_run_two_body(ora):
+    m0, m1, a, e = 1.0, 1e-3, 1.0, 0.1
+    x, v = kepler.two_body_state(m0, m1, a, e, 0.0)
+    T = 2 * math.pi * 3.3
+    out = ora.integrate_adaptive(np.array([m0, m1]), x, v, t_end=T, eta=5e-3, stop_rules=0, paper_rule=True)
+    xe, _ = kepler.two_body_state(m0, m1, a, e, T)
+    assert out["status"] == ora.DONE and out["t"] == T
+    assert np.abs(out["pos"] - xe).max() < 1e-9
