@@ -187,9 +187,14 @@ fb_status fb_ensemble_shape(const fb_ensemble *e, int32_t *n_sys, int64_t *n_bod
 fb_status fb_ensemble_destroy(fb_ensemble *e);
 
 /* ---------------------------------------------------------------- plans */
-/* The launch plan of body count n: lane mapping (FB_MAP_*), waves per
- * workgroup (1..16), and, for the persistent schedule, workgroups per CU
- * (1..32).  Plans are process-wide; the autotuner sets them. */
+/* The launch plan of body count n: lane mapping (FB_MAP_*) and waves per
+ * workgroup (1..4).  Entry n = 0 is the fused persistent launch: its mapping
+ * selects the kernel class (FB_MAP_SYSTEM_PER_LANE: full register file,
+ * system-per-lane tiles up to n = 10, n = 5 with adaptive steps or stop
+ * rules; FB_MAP_BODY_PER_LANE: <= 128 VGPRs, system-per-lane tiles only for
+ * n <= 3; FB_MAP_AUTO: the former when every bucket fits it), plus waves per
+ * workgroup and workgroups per CU (1..32, 0 = default).  Plans are
+ * process-wide; the autotuner sets them. */
 fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group,
                       int32_t groups_per_cu);
 fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,

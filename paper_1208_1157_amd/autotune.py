@@ -43,7 +43,7 @@ def apply_plans(fb, plans: dict) -> list:
     done = []
     for key, p in plans.items():
         if key == "persistent":
-            fb.set_plan(0, fb.MAP_AUTO, p["waves_per_group"], p["groups_per_cu"])
+            fb.set_plan(0, p.get("mapping", fb.MAP_AUTO), p["waves_per_group"], p["groups_per_cu"])
         else:
             fb.set_plan(int(key), p["mapping"], p["waves_per_group"], 0)
             done.append(int(key))
@@ -84,7 +84,8 @@ def tune(fb, ens, dt, target_ms=20.0, cache_path=DEFAULT_CACHE, use_cache=True, 
         if not e["chosen"]:
             continue
         if e["n"] == 0:
-            plans["persistent"] = {"waves_per_group": e["waves_per_group"], "groups_per_cu": e["groups_per_cu"]}
+            plans["persistent"] = {"mapping": e["mapping"], "waves_per_group": e["waves_per_group"],
+                                   "groups_per_cu": e["groups_per_cu"]}
         else:
             plans[str(e["n"])] = {"mapping": e["mapping"], "waves_per_group": e["waves_per_group"]}
     cache[arch] = plans
@@ -150,6 +151,7 @@ if __name__ == "__main__":
     a = ap.parse_args()
     rows, steps = sweep(fb_mod, gen_mod, a.n_lo, a.n_hi, a.per_n, a.steps)
     names = {0: "auto", 1: "system/lane", 2: "body/lane"}
+    # for the persistent rows the mapping is the fused kernel's class
     print(f"plan sweep: {a.per_n} systems per body count, {steps} fixed steps of 2pi/2000 per candidate")
     print("| n | mapping | waves/group | groups/CU | ms | algorithmic TFLOP/s | system-steps/s | chosen |")
     print("|---|---|---|---|---|---|---|---|")

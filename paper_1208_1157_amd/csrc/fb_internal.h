@@ -21,8 +21,9 @@ enum SysStatus {
 enum Mapping { MAP_SPL = 1, MAP_BPL = 2 };
 
 constexpr int kMaxBodies = 16;
-constexpr int kMaxSplBodies = 6;       // plain system-per-lane instances exist for n <= 6
-constexpr int kMaxSplPersistent = 3;   // ... and inside the fused persistent kernel for n <= 3
+constexpr int kMaxSplBodies = 10;      // plain system-per-lane instances exist for n <= 10
+constexpr int kMaxSplAdv = 5;          // ... with adaptive steps / stop rules for n <= 5
+constexpr int kMaxSplPersistent = 0;   // the body-per-lane fused class runs no system-per-lane tiles
 
 // Device view of one homogeneous body-count bucket.  Per-slot arrays have
 // `pitch` entries; slots [0, count) hold systems.
@@ -82,9 +83,13 @@ hipError_t launch_begin_run(const Bucket &B, int fixed_steps, long long n_steps,
                             hipStream_t s);
 hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group,
                         const StepParams &P, hipStream_t s);
+// spl_class: 0 = body-per-lane class fused kernel (<= 128 VGPRs; system-per-
+// lane tiles for n <= kMaxSplPersistent), 1 = system-per-lane class (full
+// register file; system-per-lane tiles for n <= kMaxSplBodies, or
+// kMaxSplAdv with adaptive steps / stop rules).
 hipError_t launch_persistent(const Bucket *d_buckets, const Tile *d_tiles,
                              const int *d_ntiles, int *d_head, const int *d_lists,
-                             const StepParams &P, int adv, int grid,
+                             const StepParams &P, int adv, int spl_class, int grid,
                              int waves_per_group, ActiveLists *compact,
                              hipStream_t s);
 hipError_t launch_build_tiles(const Bucket *d_buckets, int n_buckets,
@@ -99,7 +104,12 @@ hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos
 hipError_t launch_diag(const Bucket &B, double *energy, double *angmom,
                        hipStream_t s);
 hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s);
-size_t persistent_lds_bytes(int waves_per_group);
-int persistent_max_groups_per_cu(int adv, int waves_per_group);
+size_t persistent_lds_bytes(int spl_class, int waves_per_group);
+int persistent_max_groups_per_cu(int adv, int spl_class, int waves_per_group);
+// Largest n a persistent tile runs system-per-lane for, by kernel class.
+inline int persistent_spl_limit(int spl_class, int adv)
+{
+    return spl_class ? (adv ? kMaxSplAdv : kMaxSplBodies) : kMaxSplPersistent;
+}
 
 }  // namespace fb

@@ -27,12 +27,17 @@
 // four FMAs per component and does not need the corrected velocity.
 #include "fb_internal.h"
 
+#include <algorithm>
 #include <climits>
 
 // Partner-loop unroll of the body-per-lane evaluation: full unrolling lets
 // the scheduler hoist every partner's LDS loads and costs occupancy.
 #ifndef FB_BPL_UNROLL
 #define FB_BPL_UNROLL 2
+#endif
+// Pairs per scheduling group in the system-per-lane evaluation of n >= 5.
+#ifndef FB_SPL_PAIR_GROUP
+#define FB_SPL_PAIR_GROUP 2
 #endif
 // Waves per SIMD the register allocator targets for the body-per-lane and
 // persistent kernels.
@@ -116,6 +121,50 @@ __device__ __forceinline__ void correct_comp(const Coef &k, double bx, double bv
 {
     xc = fma(k.cxj, jk, fma(k.cxa, ak, bx));
     vc = fma(k.cvj, jk, fma(k.cva, ak, bv));
+}
+
+// One wavefront's LDS slice: the current evaluation state of its 64 lanes
+// (as 16-byte pairs so a partner costs three ds_read_b128 and one b64),
+// the masses, and two reduction scratch rows.
+struct BplLds {
+    double2 xy[64];
+    double2 zvx[64];
+    double2 vyvz[64];
+    double m[64];
+    double red[64];
+    int redi[64];
+};
+
+// System-per-lane steps of at least this many bodies park the corrector
+// bases (6 doubles per body, idle during each evaluation) in the wavefront's
+// LDS slice, so the evaluation's working set (12 doubles per body) stays in
+// VGPRs.
+#ifndef FB_SPL_LDS_MIN
+#define FB_SPL_LDS_MIN 6
+#endif
+
+// LDS bytes per wavefront a system-per-lane step of n bodies uses.
+__host__ __device__ constexpr size_t spl_lds_bytes(int n)
+{
+    return n >= FB_SPL_LDS_MIN ? (size_t)6 * n * 64 * sizeof(double) : 0;
+}
+
+// Per-wavefront LDS stride of the system-per-lane fused class, whose waves
+// may run either kind of tile side by side in one workgroup: large enough
+// for the body-per-lane slice and for the largest parked bases.
+constexpr size_t kWideLdsStride = 6 * kMaxSplBodies * 64 * sizeof(double);
+static_assert(kWideLdsStride >= sizeof(BplLds), "wide LDS stride too small");
+
+// This wavefront's slice of its workgroup's dynamic LDS, reached through
+// the module-level symbol (not a pointer argument) so separately compiled
+// tile functions still address LDS directly.  PACKED is the slice size when
+// every wave of the launch runs the same kind of tile; WIDE selects the
+// common stride of the system-per-lane fused class.
+template <size_t PACKED, bool WIDE>
+__device__ __forceinline__ char *wave_lds_base()
+{
+    extern __shared__ char fb_dyn_lds[];
+    return fb_dyn_lds + (size_t)(threadIdx.x >> 6) * (WIDE ? kWideLdsStride : PACKED);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,43 +336,82 @@ __device__ __forceinline__ void spl_accjerk(const double (&m)[N], const double (
             a[b][c] = 0.0;
             jk[b][c] = 0.0;
         }
+    // For larger systems, scheduling barriers between groups of pairs keep
+    // the scheduler from interleaving (and keeping live) every pair's
+    // temporaries at once, which would spill the system's state.
+    constexpr int kGroup = N <= 4 ? 1 << 20 : FB_SPL_PAIR_GROUP;
 #pragma unroll
     for (int i = 1; i < N; ++i)
 #pragma unroll
-        for (int j = i + 1; j < N; ++j)
+        for (int j = i + 1; j < N; ++j) {
             spl_pair<N, TS>(i, j, m, x, v, a, jk, wmax);
+            if (((i - 1) * (2 * N - i - 2) / 2 + (j - i)) % kGroup == 0)
+                __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
-    for (int j = 1; j < N; ++j)
+    for (int j = 1; j < N; ++j) {
         spl_pair<N, TS>(0, j, m, x, v, a, jk, wmax);
+        if (j % kGroup == 0)
+            __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // One P(EC)^2 step of size h.  On entry (a, jk) hold the carried a0, j0; on
 // exit (x, v) are the corrected state and (a, jk) the last evaluation.
 // Returns the step-rule quantity of the last evaluation (TS only).
-template <int N, bool TS>
+template <int N, bool TS, bool WIDE>
 __device__ __forceinline__ double spl_step(const double (&m)[N], double (&x)[N][3],
                                            double (&v)[N][3], double (&a)[N][3],
                                            double (&jk)[N][3], const Coef &k)
 {
+    constexpr bool kPark = N >= FB_SPL_LDS_MIN;
+    // this wavefront's parking area: [6N][64] doubles, lane fastest
+    double *park = reinterpret_cast<double *>(wave_lds_base<spl_lds_bytes(N), WIDE>()) +
+                   (threadIdx.x & 63);
     double bx[N][3], bv[N][3], xc[N][3], vc[N][3];
 #pragma unroll
     for (int b = 0; b < N; ++b)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) {
             predict_comp(k, x[b][c], v[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c], bx[b][c],
                          bv[b][c]);
+            if (kPark) {
+                park[(6 * b + c) * 64] = bx[b][c];
+                park[(6 * b + 3 + c) * 64] = bv[b][c];
+            }
+        }
+    // The clobbers keep the compiler from forwarding the parked values
+    // (which would keep them in registers) or hoisting their reloads above
+    // the evaluation.
+    if (kPark)
+        __asm__ __volatile__("" ::: "memory");
     double w = 0.0;
     spl_accjerk<N, false>(m, xc, vc, a, jk, w);
-#pragma unroll
-    for (int b = 0; b < N; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            correct_comp(k, bx[b][c], bv[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c]);
-    spl_accjerk<N, TS>(m, xc, vc, a, jk, w);
+    if (kPark)
+        __asm__ __volatile__("" ::: "memory");
 #pragma unroll
     for (int b = 0; b < N; ++b)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            if (kPark) {
+                bx[b][c] = park[(6 * b + c) * 64];
+                bv[b][c] = park[(6 * b + 3 + c) * 64];
+            }
+            correct_comp(k, bx[b][c], bv[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c]);
+        }
+    if (kPark)
+        __asm__ __volatile__("" ::: "memory");
+    spl_accjerk<N, TS>(m, xc, vc, a, jk, w);
+    if (kPark)
+        __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (kPark) {
+                bx[b][c] = park[(6 * b + c) * 64];
+                bv[b][c] = park[(6 * b + 3 + c) * 64];
+            }
             correct_comp(k, bx[b][c], bv[b][c], a[b][c], jk[b][c], xc[b][c], vc[b][c]);
             x[b][c] = xc[b][c];
             v[b][c] = vc[b][c];
@@ -401,8 +489,8 @@ __device__ __forceinline__ double paper_dt(const double (&a)[N][3], const double
 }
 
 // Integrate one system (one lane) for at most P.quantum steps.
-template <int N, bool ADV>
-__device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
+template <int N, bool ADV, bool WIDE>
+__device__ __forceinline__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
 {
     Clock c = load_clock(B, slot);
     if (c.status != ST_ACTIVE)
@@ -421,49 +509,71 @@ __device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
             jk[b][cc] = st[((R_J + cc) * N + b) * pitch + slot];
         }
     }
-    int quantum = P.quantum;
     if (!ADV) {
-        // whole steps of the run with no per-step bookkeeping
-        long long whole = c.nfull - c.k;
-        whole = whole < 0 ? 0 : whole;
-        whole = min(whole, (long long)quantum);
-        whole = min(whole, P.max_steps - c.steps);
-        const int nrun = whole > 0 ? (int)whole : 0;
-        const Coef k = make_coef(c.dt);
-#pragma unroll 2
-        for (int q = 0; q < nrun; ++q)
-            (void)spl_step<N, false>(m, x, v, a, jk, k);
-        if (nrun > 0) {
-            c.k += nrun;
-            c.steps += nrun;
-            c.t = fma((double)c.k, c.dt, c.t0);
-            if (c.k >= c.nfull) {
+        // Fixed step.  Segment 0 runs the run's whole steps with no per-step
+        // bookkeeping; segment 1 the shortened final step, if one is due.
+        // One loop serves both so the step body is instantiated once.
+        int budget = P.quantum;
+#pragma unroll 1
+        for (int seg = 0; seg < 2 && c.status == ST_ACTIVE && budget > 0; ++seg) {
+            long long cnt = 0;
+            double h = c.dt;
+            if (seg == 0) {
+                cnt = c.nfull - c.k;
+                cnt = cnt < 0 ? 0 : cnt;
+            } else {
                 const double rem = c.t_end - c.t;
-                if (!(rem * c.dt > 1e-9 * c.dt * c.dt)) {
+                if (rem * c.dt > 1e-9 * c.dt * c.dt) {
+                    cnt = 1;
+                    h = rem;
+                } else {
                     c.t = c.t_end;
                     c.status = ST_DONE;
                 }
             }
+            cnt = min(cnt, (long long)budget);
+            cnt = min(cnt, P.max_steps - c.steps);
+            const int nrun = cnt > 0 ? (int)cnt : 0;
+            const Coef k = make_coef(h);
+            constexpr int kStepUnroll = N <= 4 ? 2 : 1;
+#pragma unroll kStepUnroll
+            for (int q = 0; q < nrun; ++q)
+                (void)spl_step<N, false, WIDE>(m, x, v, a, jk, k);
+            budget -= nrun;
+            c.steps += nrun;
+            if (seg == 0) {
+                c.k += nrun;
+                if (nrun > 0)
+                    c.t = fma((double)c.k, c.dt, c.t0);
+                if (c.k >= c.nfull) {
+                    const double rem = c.t_end - c.t;
+                    if (!(rem * c.dt > 1e-9 * c.dt * c.dt)) {
+                        c.t = c.t_end;
+                        c.status = ST_DONE;
+                    }
+                }
+            } else if (nrun > 0) {
+                c.t = c.t_end;
+                c.status = ST_DONE;
+            }
+            if (c.status == ST_ACTIVE && c.steps >= P.max_steps)
+                c.status = ST_MAXSTEPS;
         }
-        quantum -= nrun;
-    }
-    for (int q = 0; q < quantum; ++q) {
-        double h = 0.0;
-        bool last = false;
-        if (!plan_step(c, P, h, last))
-            break;
-        const double w = spl_step<N, ADV>(m, x, v, a, jk, make_coef(h));
-        double dtp = 0.0;
-        if (ADV)
-            dtp = P.adaptive == 2 ? paper_dt<N>(a, jk, P.eta) : P.eta * rsqrt_nr(w);
-        finish_step(c, P, last, h, dtp);
-        if (ADV) {
+    } else {
+        for (int q = 0; q < P.quantum; ++q) {
+            double h = 0.0;
+            bool last = false;
+            if (!plan_step(c, P, h, last))
+                break;
+            const double w = spl_step<N, true, WIDE>(m, x, v, a, jk, make_coef(h));
+            double dtp = P.adaptive == 2 ? paper_dt<N>(a, jk, P.eta) : P.eta * rsqrt_nr(w);
+            finish_step(c, P, last, h, dtp);
             const int fl = spl_stop_flags<N>(m, x, v, P);
             if (fl)
                 c.status = status_of_flags(fl);
+            if (c.status != ST_ACTIVE)
+                break;
         }
-        if (c.status != ST_ACTIVE)
-            break;
     }
     if (!ADV) {
         bool fin = true;
@@ -489,26 +599,6 @@ __device__ void spl_run(const Bucket &B, const int slot, const StepParams &P)
 // body-per-lane (BPL)
 // ---------------------------------------------------------------------------
 
-// One wavefront's LDS slice: the current evaluation state of its 64 lanes
-// (as 16-byte pairs so a partner costs three ds_read_b128 and one b64),
-// the masses, and two reduction scratch rows.
-struct BplLds {
-    double2 xy[64];
-    double2 zvx[64];
-    double2 vyvz[64];
-    double m[64];
-    double red[64];
-    int redi[64];
-};
-
-// This wavefront's slice of the dynamic LDS of its workgroup.  Reached
-// through the module-level symbol (not passed as a pointer) so that code in
-// separately compiled tile functions still addresses LDS directly.
-__device__ __forceinline__ BplLds &wave_lds()
-{
-    extern __shared__ BplLds fb_dyn_lds[];
-    return fb_dyn_lds[threadIdx.x >> 6];
-}
 
 // k-th planet partner of planet b (0 <= k < n-2).
 __device__ __forceinline__ int planet_partner(const int k, const int b)
@@ -662,12 +752,12 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
 // control flow (the LDS exchanges need it); lanes of finished, padding or
 // absent systems compute but never commit.  Returns, on the star lane of each
 // present system, whether that system is still active.
-template <int N, bool ADV>
-__device__ bool bpl_run(const Bucket &B, const int first, const int count, const int *list,
+template <int N, bool ADV, bool WIDE>
+__device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const int count, const int *list,
                         const StepParams &P, int &slot_out)
 {
     constexpr int S = 64 / N;
-    BplLds &L = wave_lds();
+    BplLds &L = *reinterpret_cast<BplLds *>(wave_lds_base<sizeof(BplLds), WIDE>());
     const int lane = threadIdx.x & 63;
     const int braw = lane / S;
     const int b = braw < N ? braw : N - 1;
@@ -766,7 +856,7 @@ __global__ __launch_bounds__(256) void k_plain_spl(Bucket B, StepParams P)
 {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot < B.count)
-        spl_run<N, ADV>(B, slot, P);
+        spl_run<N, ADV, false>(B, slot, P);
 }
 
 template <int N, bool ADV>
@@ -781,7 +871,7 @@ void k_plain_bpl(Bucket B, StepParams P)
         return;
     const int count = min(S, B.count - first);
     int slot;
-    bpl_run<N, ADV>(B, first, count, nullptr, P, slot);
+    bpl_run<N, ADV, false>(B, first, count, nullptr, P, slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -816,32 +906,53 @@ __device__ __noinline__ bool spl_tile(const Bucket &B, const Tile &T, const int 
     if (lane >= T.count)
         return false;
     slot = list ? list[T.first + lane] : T.first + lane;
-    spl_run<N, ADV>(B, slot, P);
+    spl_run<N, ADV, true>(B, slot, P);
     return B.status[slot] == ST_ACTIVE;
 }
 
-template <int N, bool ADV>
+// CLS only separates the instances used by the two fused-kernel classes, so
+// each is compiled under its own kernel's register budget.
+template <int N, bool ADV, bool CLS>
 __device__ __noinline__ bool bpl_tile(const Bucket &B, const Tile &T, const int *list,
                                       const StepParams &P, int &slot)
 {
-    return bpl_run<N, ADV>(B, T.first, T.count, list, P, slot);
+    return bpl_run<N, ADV, CLS>(B, T.first, T.count, list, P, slot);
 }
 
-template <bool ADV>
+// Tile dispatch.  The body-per-lane class (SPLC false) keeps the fused
+// kernel at <= 128 VGPRs (4 waves per SIMD) and runs every tile body-per-
+// lane; the system-per-lane class gives the kernel the full register file
+// (1 wave per SIMD) and runs system-per-lane tiles up to n = 10 (n = 5 with
+// adaptive steps / stop rules), body-per-lane beyond.
+template <bool ADV, bool SPLC>
 __device__ __forceinline__ bool run_tile(const Bucket &B, const Tile &T, const int *list,
                                          const StepParams &P, int &slot)
 {
     const int map = T.kind >> 5;
     const int n = T.kind & 31;
     if (map == MAP_SPL) {
-        switch (n) {
-        case 2: return spl_tile<2, ADV>(B, T, list, P, slot);
-        case 3: return spl_tile<3, ADV>(B, T, list, P, slot);
-        default: break;
+        if constexpr (SPLC) {
+            switch (n) {
+            case 2: return spl_tile<2, ADV>(B, T, list, P, slot);
+            case 3: return spl_tile<3, ADV>(B, T, list, P, slot);
+            case 4: return spl_tile<4, ADV>(B, T, list, P, slot);
+            case 5: return spl_tile<5, ADV>(B, T, list, P, slot);
+            default: break;
+            }
+            if constexpr (!ADV) {
+                switch (n) {
+                case 6: return spl_tile<6, false>(B, T, list, P, slot);
+                case 7: return spl_tile<7, false>(B, T, list, P, slot);
+                case 8: return spl_tile<8, false>(B, T, list, P, slot);
+                case 9: return spl_tile<9, false>(B, T, list, P, slot);
+                case 10: return spl_tile<10, false>(B, T, list, P, slot);
+                default: break;
+                }
+            }
         }
     }
     switch (n) {
-#define FB_BPL_CASE(NN) case NN: return bpl_tile<NN, ADV>(B, T, list, P, slot);
+#define FB_BPL_CASE(NN) case NN: return bpl_tile<NN, ADV, SPLC>(B, T, list, P, slot);
         FB_BPL_CASE(2) FB_BPL_CASE(3) FB_BPL_CASE(4) FB_BPL_CASE(5) FB_BPL_CASE(6)
         FB_BPL_CASE(7) FB_BPL_CASE(8) FB_BPL_CASE(9) FB_BPL_CASE(10) FB_BPL_CASE(11)
         FB_BPL_CASE(12) FB_BPL_CASE(13) FB_BPL_CASE(14) FB_BPL_CASE(15) FB_BPL_CASE(16)
@@ -850,11 +961,12 @@ __device__ __forceinline__ bool run_tile(const Bucket &B, const Tile &T, const i
     }
 }
 
-template <bool ADV, bool COMPACT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FB_BPL_WAVES)))
-void k_persistent(const Bucket *__restrict__ buckets, const Tile *__restrict__ tiles,
-                  const int *__restrict__ ntiles_p, int *__restrict__ head, const int *lists,
-                  StepParams P, ActiveLists AL)
+template <bool ADV, bool COMPACT, bool SPLC>
+__device__ __forceinline__ void persistent_body(const Bucket *__restrict__ buckets,
+                                                const Tile *__restrict__ tiles,
+                                                const int *__restrict__ ntiles_p,
+                                                int *__restrict__ head, const int *lists,
+                                                const StepParams &P, const ActiveLists &AL)
 {
     const int ntiles = *ntiles_p;
     const int lane = threadIdx.x & 63;
@@ -868,10 +980,30 @@ void k_persistent(const Bucket *__restrict__ buckets, const Tile *__restrict__ t
         const Tile T = tiles[t];
         const Bucket B = buckets[T.bucket];
         int slot = 0;
-        const bool keep = run_tile<ADV>(B, T, lists, P, slot);
+        const bool keep = run_tile<ADV, SPLC>(B, T, lists, P, slot);
         if (COMPACT)
             append_survivors(AL, T.bucket, keep, slot);
     }
+}
+
+template <bool ADV, bool COMPACT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FB_BPL_WAVES)))
+void k_persistent(const Bucket *__restrict__ buckets, const Tile *__restrict__ tiles,
+                  const int *__restrict__ ntiles_p, int *__restrict__ head, const int *lists,
+                  StepParams P, ActiveLists AL)
+{
+    persistent_body<ADV, COMPACT, false>(buckets, tiles, ntiles_p, head, lists, P, AL);
+}
+
+template <bool ADV, bool COMPACT>
+__global__ __launch_bounds__(256) void k_persistent_spl(const Bucket *__restrict__ buckets,
+                                                        const Tile *__restrict__ tiles,
+                                                        const int *__restrict__ ntiles_p,
+                                                        int *__restrict__ head,
+                                                        const int *lists, StepParams P,
+                                                        ActiveLists AL)
+{
+    persistent_body<ADV, COMPACT, true>(buckets, tiles, ntiles_p, head, lists, P, AL);
 }
 
 // Tiles for the next quantum from the survivor counts (one workgroup):
@@ -1201,20 +1333,38 @@ hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const
         return hipSuccess;
     const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
     const bool adv = P.adaptive || P.stop_rules;
-    if (mapping == MAP_SPL && B.n <= kMaxSplBodies) {
+    if (mapping == MAP_SPL && B.n <= (adv ? kMaxSplAdv : kMaxSplBodies)) {
         const dim3 grid = grid_for(B.count, 64 * W);
-#define FB_L(NN)                                                                        \
-    if (adv) hipLaunchKernelGGL((k_plain_spl<NN, true>), grid, dim3(64 * W), 0, s, B, P);  \
-    else hipLaunchKernelGGL((k_plain_spl<NN, false>), grid, dim3(64 * W), 0, s, B, P)
-        switch (B.n) {
-        case 2: FB_L(2); break;
-        case 3: FB_L(3); break;
-        case 4: FB_L(4); break;
-        case 5: FB_L(5); break;
-        case 6: FB_L(6); break;
-        default: return hipErrorInvalidValue;
+#define FB_LA(NN)                                                                       \
+    hipLaunchKernelGGL((k_plain_spl<NN, true>), grid, dim3(64 * W), spl_lds_bytes(NN) * W, \
+                       s, B, P)
+#define FB_LF(NN)                                                                       \
+    hipLaunchKernelGGL((k_plain_spl<NN, false>), grid, dim3(64 * W), spl_lds_bytes(NN) * W, \
+                       s, B, P)
+        if (adv) {
+            switch (B.n) {
+            case 2: FB_LA(2); break;
+            case 3: FB_LA(3); break;
+            case 4: FB_LA(4); break;
+            case 5: FB_LA(5); break;
+            default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (B.n) {
+            case 2: FB_LF(2); break;
+            case 3: FB_LF(3); break;
+            case 4: FB_LF(4); break;
+            case 5: FB_LF(5); break;
+            case 6: FB_LF(6); break;
+            case 7: FB_LF(7); break;
+            case 8: FB_LF(8); break;
+            case 9: FB_LF(9); break;
+            case 10: FB_LF(10); break;
+            default: return hipErrorInvalidValue;
+            }
         }
-#undef FB_L
+#undef FB_LA
+#undef FB_LF
         return hipGetLastError();
     }
     const int S = 64 / B.n;
@@ -1229,45 +1379,57 @@ hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const
     return hipGetLastError();
 }
 
-size_t persistent_lds_bytes(int waves_per_group) { return sizeof(BplLds) * waves_per_group; }
+size_t persistent_lds_bytes(int spl_class, int waves_per_group)
+{
+    const size_t per_wave = spl_class ? kWideLdsStride : sizeof(BplLds);
+    return per_wave * waves_per_group;
+}
 
-int persistent_max_groups_per_cu(int adv, int waves_per_group)
+int persistent_max_groups_per_cu(int adv, int spl_class, int waves_per_group)
 {
     int blocks = 0;
     const int threads = 64 * waves_per_group;
-    const size_t lds = persistent_lds_bytes(waves_per_group);
+    const size_t lds = persistent_lds_bytes(spl_class, waves_per_group);
     hipError_t e;
-    if (adv)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<true, true>,
-                                                         threads, lds);
+    if (spl_class)
+        e = adv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent_spl<true, true>,
+                                                               threads, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent_spl<false, false>,
+                                                               threads, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<false, false>,
-                                                         threads, lds);
+        e = adv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<true, true>,
+                                                               threads, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<false, false>,
+                                                               threads, lds);
     return e == hipSuccess ? blocks : 0;
 }
 
 hipError_t launch_persistent(const Bucket *d_buckets, const Tile *d_tiles, const int *d_ntiles,
                              int *d_head, const int *d_lists, const StepParams &P, int adv,
-                             int grid, int waves_per_group, ActiveLists *compact, hipStream_t s)
+                             int spl_class, int grid, int waves_per_group, ActiveLists *compact,
+                             hipStream_t s)
 {
     const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
-    const size_t lds = persistent_lds_bytes(W);
+    const size_t lds = persistent_lds_bytes(spl_class, W);
     ActiveLists AL = compact ? *compact : ActiveLists{nullptr, nullptr, nullptr, nullptr, nullptr};
-    if (adv) {
-        if (compact)
-            hipLaunchKernelGGL((k_persistent<true, true>), dim3(grid), dim3(64 * W), lds, s,
-                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
-        else
-            hipLaunchKernelGGL((k_persistent<true, false>), dim3(grid), dim3(64 * W), lds, s,
-                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
+    const dim3 g(grid), b(64 * W);
+#define FB_P(KERNEL, A, C)                                                               \
+    hipLaunchKernelGGL((KERNEL<A, C>), g, b, lds, s, d_buckets, d_tiles, d_ntiles, d_head, \
+                       d_lists, P, AL)
+    if (spl_class) {
+        if (adv) {
+            if (compact) FB_P(k_persistent_spl, true, true); else FB_P(k_persistent_spl, true, false);
+        } else {
+            if (compact) FB_P(k_persistent_spl, false, true); else FB_P(k_persistent_spl, false, false);
+        }
     } else {
-        if (compact)
-            hipLaunchKernelGGL((k_persistent<false, true>), dim3(grid), dim3(64 * W), lds, s,
-                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
-        else
-            hipLaunchKernelGGL((k_persistent<false, false>), dim3(grid), dim3(64 * W), lds, s,
-                               d_buckets, d_tiles, d_ntiles, d_head, d_lists, P, AL);
+        if (adv) {
+            if (compact) FB_P(k_persistent, true, true); else FB_P(k_persistent, true, false);
+        } else {
+            if (compact) FB_P(k_persistent, false, true); else FB_P(k_persistent, false, false);
+        }
     }
+#undef FB_P
     return hipGetLastError();
 }
 

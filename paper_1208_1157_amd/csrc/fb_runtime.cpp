@@ -69,7 +69,7 @@ void init_plans_locked()
         return;
     for (int n = 0; n <= kMaxBodies; ++n)
         g_plan[n] = Plan{n <= 3 ? MAP_SPL : MAP_BPL, n <= 3 ? 4 : 2, 0};
-    g_plan[0] = Plan{MAP_BPL, 2, 8};
+    g_plan[0] = Plan{0, 2, 8};   // fused-kernel class chosen per launch
     g_plan_init = true;
 }
 }  // namespace
@@ -443,8 +443,10 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     const int W = std::max(1, std::min(4, p0.waves_per_group));
     const bool adv = o.adaptive || o.stop_rules;
     const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
+    const int cls = persistent_class(p0, e->buckets, adv, e->num_cu);
+    const int spl_lim = persistent_spl_limit(cls, adv ? 1 : 0);
     int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
-    const int occ = persistent_max_groups_per_cu(adv ? 1 : 0, W);
+    const int occ = persistent_max_groups_per_cu(adv ? 1 : 0, cls, W);
     if (occ > 0)
         gpc = std::min(gpc, occ);
     const int grid = std::max(1, gpc * e->num_cu);
@@ -455,7 +457,8 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     for (int i = 0; i < nbk; ++i) {
         const int n = e->buckets[i].n;
         const int m = get_plan(n).mapping;
-        mapping[i] = (m == MAP_SPL && n <= kMaxSplPersistent) ? MAP_SPL : MAP_BPL;
+        // in the system-per-lane class every bucket that can runs system-per-lane
+        mapping[i] = (n <= spl_lim && (m == MAP_SPL || cls == 1)) ? MAP_SPL : MAP_BPL;
         counts[i] = e->buckets[i].count;
     }
     ident.reserve(e->L.list_total);
@@ -493,7 +496,7 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
             return err;
         ActiveLists al = AL[k];
         return launch_persistent(e->d_buckets, e->d_tiles, d_ntiles, d_head, e->d_lists[k], P,
-                                 adv ? 1 : 0, grid, W, compact ? &al : nullptr, s);
+                                 adv ? 1 : 0, cls, grid, W, compact ? &al : nullptr, s);
     };
 
     if (quantum == INT_MAX) {
@@ -854,13 +857,15 @@ fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group, int32
         return fail(FB_E_INVAL, "waves_per_group must be 1..4");
     if (groups_per_cu < 0 || groups_per_cu > 32)
         return fail(FB_E_INVAL, "groups_per_cu must be 0..32");
-    if (mapping == FB_MAP_SYSTEM_PER_LANE && n > kMaxSplBodies)
+    if (mapping == FB_MAP_SYSTEM_PER_LANE && n > 0 && n > kMaxSplBodies)
         return fail(FB_E_INVAL, "system-per-lane is built for n <= %d", kMaxSplBodies);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     init_plans_locked();
     Plan &p = g_plan[n];
     if (mapping != FB_MAP_AUTO)
         p.mapping = mapping == FB_MAP_SYSTEM_PER_LANE ? MAP_SPL : MAP_BPL;
+    else if (n == 0)
+        p.mapping = 0;
     p.waves_per_group = waves_per_group;
     p.groups_per_cu = groups_per_cu;
     return FB_OK;
@@ -873,7 +878,8 @@ fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
         return fail(FB_E_INVAL, "plan index must be 0 or 2..%d", kMaxBodies);
     const Plan p = get_plan(n);
     if (mapping)
-        *mapping = p.mapping == MAP_SPL ? FB_MAP_SYSTEM_PER_LANE : FB_MAP_BODY_PER_LANE;
+        *mapping = p.mapping == MAP_SPL ? FB_MAP_SYSTEM_PER_LANE
+                   : p.mapping == MAP_BPL ? FB_MAP_BODY_PER_LANE : FB_MAP_AUTO;
     if (waves_per_group)
         *waves_per_group = p.waves_per_group;
     if (groups_per_cu)
@@ -959,12 +965,14 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         po.schedule = FB_SCHED_PERSISTENT;
         double best = 1e300;
         size_t best_i = 0;
+        for (int cls : {0, 1})
         for (int W : {1, 2, 4}) {
-            const int occ = persistent_max_groups_per_cu(0, W);
+            const int occ = persistent_max_groups_per_cu(0, cls, W);
             for (int g : {1, 2, 4, 8, 16, 32}) {
                 if (occ > 0 && g > occ)
                     continue;
-                fb_status st = fb_set_plan(0, FB_MAP_AUTO, W, g);
+                const int cmap = cls ? FB_MAP_SYSTEM_PER_LANE : FB_MAP_BODY_PER_LANE;
+                fb_status st = fb_set_plan(0, cmap, W, g);
                 if (st != FB_OK)
                     return st;
                 FB_HIP(restore());
@@ -981,7 +989,7 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
                 fb_tune_entry t;
                 std::memset(&t, 0, sizeof t);
                 t.n = 0;
-                t.mapping = FB_MAP_AUTO;
+                t.mapping = cmap;
                 t.waves_per_group = W;
                 t.groups_per_cu = g;
                 t.ms = ms;
@@ -994,7 +1002,7 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         }
         (void)keep0;
         entries[best_i].chosen = 1;
-        fb_status st = fb_set_plan(0, FB_MAP_AUTO, entries[best_i].waves_per_group,
+        fb_status st = fb_set_plan(0, entries[best_i].mapping, entries[best_i].waves_per_group,
                                    entries[best_i].groups_per_cu);
         if (st != FB_OK)
             return st;

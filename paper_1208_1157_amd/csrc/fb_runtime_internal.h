@@ -26,11 +26,34 @@ fb_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 struct Plan {
-    int mapping;          // MAP_SPL / MAP_BPL
+    int mapping;          // MAP_SPL / MAP_BPL (entry 0: fused-kernel class, 0 = auto)
     int waves_per_group;  // 1..4
     int groups_per_cu;    // persistent schedule only (entry 0)
 };
 Plan get_plan(int n);
+
+// Fused persistent kernel class for a launch over buckets of these body
+// counts: the plan's choice, or (auto) the system-per-lane class when every
+// bucket can run system-per-lane in it and its tiles (64 systems each) give
+// every SIMD of the device a wavefront; that class runs one wavefront per
+// SIMD, so with fewer tiles the body-per-lane class, which spreads a system
+// over n lanes, keeps more of the device busy.
+template <class BucketRange>
+int persistent_class(const Plan &p0, const BucketRange &buckets, bool adv, int num_cu)
+{
+    if (p0.mapping == MAP_SPL)
+        return 1;
+    if (p0.mapping == MAP_BPL)
+        return 0;
+    const int lim = persistent_spl_limit(1, adv ? 1 : 0);
+    long long tiles = 0;
+    for (const Bucket &B : buckets) {
+        if (B.n > lim)
+            return 0;
+        tiles += (B.count + 63) / 64;
+    }
+    return tiles >= 4LL * num_cu ? 1 : 0;
+}
 
 // Brackets the integration launches enqueued in its scope with HIP events on
 // `s` when the kernel timer is enabled.

@@ -266,6 +266,12 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
     std::vector<Item> items;
     S->h_buckets.clear();
     sys_steps = 0.0;
+    // The fused-kernel class is fixed by the plan (auto: body-per-lane), never
+    // by the resident mix, so every request sees the same arithmetic alone
+    // and among others.
+    const Plan p0 = get_plan(0);
+    const int cls = p0.mapping == MAP_SPL ? 1 : 0;
+    const int spl_lim = persistent_spl_limit(cls, 0);
     for (Request *R : S->resident) {
         const long long left = R->total_steps - R->done_steps;
         const long long adv = std::min<long long>(left, Q);
@@ -274,7 +280,7 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
             const int bi = (int)S->h_buckets.size();
             S->h_buckets.push_back(B);
             const Plan p = get_plan(B.n);
-            const int map = (p.mapping == MAP_SPL && B.n <= kMaxSplPersistent) ? MAP_SPL : MAP_BPL;
+            const int map = (B.n <= spl_lim && (p.mapping == MAP_SPL || cls == 1)) ? MAP_SPL : MAP_BPL;
             const int cap = tile_systems(map, B.n);
             for (int f = 0; f < B.count; f += cap) {
                 Item it;
@@ -311,16 +317,15 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
         P.max_steps = LLONG_MAX;
         P.quantum = Q;
         P.pad = 0;
-        const Plan p0 = get_plan(0);
         const int W = std::max(1, std::min(4, p0.waves_per_group));
         int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
-        const int occ = persistent_max_groups_per_cu(0, W);
+        const int occ = persistent_max_groups_per_cu(0, cls, W);
         if (occ > 0)
             gpc = std::min(gpc, occ);
         const int grid = std::max(1, std::min(gpc * S->num_cu, nt));
         ProfScope ps(S->stream);
         FB_HIP(launch_persistent(S->d_buckets, S->d_tiles, S->d_ints, S->d_ints + 1, nullptr, P, 0,
-                                 grid, W, nullptr, S->stream));
+                                 cls, grid, W, nullptr, S->stream));
     }
     for (Request *R : S->resident) {
         R->done_steps = std::min(R->total_steps, R->done_steps + Q);

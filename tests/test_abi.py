@@ -94,7 +94,7 @@ def test_plan_table(fbmod):
     assert fbmod.get_plan(5) == (fbmod.MAP_SPL, 2, 0)
     fbmod.set_plan(5, m0[0], m0[1], m0[2])
     with pytest.raises(fbmod.FewbodyError):
-        fbmod.set_plan(9, fbmod.MAP_SPL, 1, 0)      # SPL built for n <= 6 only
+        fbmod.set_plan(12, fbmod.MAP_SPL, 1, 0)     # SPL built for n <= 10 only
     with pytest.raises(fbmod.FewbodyError):
         fbmod.set_plan(1, fbmod.MAP_BPL, 1, 0)
     with pytest.raises(fbmod.FewbodyError):

@@ -18,11 +18,11 @@ class RecordingPlans:
 def test_apply_plans_installs_every_entry():
     fb = RecordingPlans()
     plans = {"3": {"mapping": 1, "waves_per_group": 2}, "9": {"mapping": 2, "waves_per_group": 4},
-             "persistent": {"waves_per_group": 4, "groups_per_cu": 8}}
+             "persistent": {"mapping": 1, "waves_per_group": 4, "groups_per_cu": 8}}
     done = autotune.apply_plans(fb, plans)
     assert sorted(done) == [3, 9]
     assert (3, 1, 2, 0) in fb.calls and (9, 2, 4, 0) in fb.calls
-    assert (0, 0, 4, 8) in fb.calls
+    assert (0, 1, 4, 8) in fb.calls
 
 
 def test_cache_roundtrip(tmp_path):

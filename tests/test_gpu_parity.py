@@ -59,14 +59,20 @@ def test_parity_three_body_1024(plans, ora, mapping):
 
 
 @pytest.mark.parametrize("sched", ["plain", "persistent", "persistent_compact"])
-@pytest.mark.parametrize("mapping", ["spl", "bpl"])
+@pytest.mark.parametrize("mapping", ["spl", "bpl", "splclass"])
 def test_parity_ragged_all_body_counts(plans, ora, sched, mapping):
     """n = 2..16 with ragged tails in every bucket, both mappings (SPL where
-    built), both schedules, quanta that do not divide the step count."""
+    built), both schedules, quanta that do not divide the step count.
+    'splclass' forces the full-register fused kernel, where waves of one
+    workgroup run system-per-lane and body-per-lane tiles side by side."""
     fb = plans
     for n in range(2, 17):
-        use_spl = mapping == "spl" and n <= 6
+        use_spl = mapping in ("spl", "splclass") and n <= 10
         fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
+    if mapping == "splclass":
+        fb.set_plan(0, fb.MAP_SPL, 4, 8)
+    elif mapping == "bpl":
+        fb.set_plan(0, fb.MAP_BPL, 2, 8)
     ens = gen.ragged_hill(400, seed=7, n_lo=2, n_hi=16)
     steps = 300
     opts = None
@@ -168,10 +174,17 @@ def test_determinism_and_chunking_invariance(fb):
     assert np.all(c["steps"] == 400)
 
 
-def test_persistent_equals_plain_bitwise(plans):
+@pytest.mark.parametrize("cls", ["bpl", "spl"])
+def test_persistent_equals_plain_bitwise(plans, cls):
+    """Same mapping per body count in both schedules -> identical bits, in
+    either fused-kernel class (the SPL class mixes both kinds of tile)."""
     fb = plans
+    for n in range(2, 17):
+        use_spl = cls == "spl" and n <= 10
+        fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
+    fb.set_plan(0, fb.MAP_SPL if cls == "spl" else fb.MAP_BPL, 4, 8)
     ens = gen.ragged_hill(300, seed=11, n_lo=3, n_hi=12)
-    say("persistent vs plain bitwise")
+    say("persistent vs plain bitwise", cls)
     a, _, _ = run_gpu(fb, ens, 150, H2000)
     for compact in (False, True):
         o = fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=40, compact=compact)
