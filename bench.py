@@ -145,12 +145,24 @@ def lifetimes_extras(fb, gen, torch, log, orbits=100.0, quantum=2000):
     return out
 
 
-def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000):
+def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, policy="srpt",
+                   cls="bpl", quantum_tiles=0, long_steps=0):
     from paper_1208_1157_amd import serve
     trace = gen.serving_trace(n_req, rate=200.0, seed=4)
-    rep = serve.run_trace(fb, trace, max_resident=max_resident, steps_per_quantum=quantum, log=log)
+    saved = fb.get_plan(0)
+    fb.set_plan(0, fb.MAP_SPL if cls == "spl" else fb.MAP_BPL, saved[1], saved[2])
+    try:
+        rep = serve.run_trace(fb, trace, max_resident=max_resident, steps_per_quantum=quantum, log=log,
+                              policy=fb.POLICY_SRPT if policy == "srpt" else fb.POLICY_FAIR,
+                              quantum_tiles=quantum_tiles, long_steps=long_steps)
+    finally:
+        fb.set_plan(0, *saved)
     rep["max_resident"] = max_resident
     rep["steps_per_quantum"] = quantum
+    rep["policy"] = policy
+    rep["fused_class"] = "system-per-lane" if cls == "spl" else "body-per-lane"
+    rep["quantum_tiles"] = quantum_tiles
+    rep["long_steps"] = long_steps
     rep["workload"] = (f"serving: {n_req} requests, Poisson 200 req/s, 1..4096 systems (log-uniform) of 3..10 "
                        f"bodies, t_end 2pi*10^U(1,3), dt 2pi/1000")
     return rep
@@ -171,6 +183,14 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-max-resident", type=int, default=4096)
     ap.add_argument("--serve-quantum", type=int, default=2000)
+    ap.add_argument("--serve-policy", choices=["fair", "srpt"], default="srpt",
+                    help="server scheduling: every resident request per quantum, or least remaining work first")
+    ap.add_argument("--serve-class", choices=["bpl", "spl"], default="bpl",
+                    help="fused-kernel class the server runs")
+    ap.add_argument("--serve-quantum-tiles", type=int, default=0,
+                    help="SRPT tiles per quantum (0: the server's default)")
+    ap.add_argument("--serve-long-steps", type=int, default=0,
+                    help="SRPT: requests with at least this many steps left run every quantum")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -259,7 +279,9 @@ def main():
 
     extras = {}
     if not args.no_serve:
-        rep = serving_report(fb, gen, log, args.serve_requests, args.serve_max_resident, args.serve_quantum)
+        rep = serving_report(fb, gen, log, args.serve_requests, args.serve_max_resident, args.serve_quantum,
+                             args.serve_policy, args.serve_class, args.serve_quantum_tiles,
+                             args.serve_long_steps)
         result["p50_latency_s"] = rep["p50_latency_s"]
         result["p99_latency_s"] = rep["p99_latency_s"]
         extras["serving"] = rep

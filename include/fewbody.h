@@ -235,24 +235,38 @@ fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
 /* A continuous-batching integration server.  Requests (an ensemble with its
  * own destination time and fixed step, integrated as fb_integrate does with
  * the persistent schedule) are queued from any thread and served by one
- * worker thread in quanta: queued requests are admitted in arrival order
- * while their device state fits the memory budget and the resident cap;
- * every quantum advances all resident systems by up to steps_per_quantum
- * steps in one fused launch; finished requests are copied back and their
- * memory is reused.  A request's results do not depend on what else is
- * resident.  (No counterpart in the paper, whose host only sets up, loads,
- * calls and examines -- Section 5.3; this is the serving form of its many
- * steps per kernel call.) */
+ * worker thread in quanta.  Queued requests are admitted in arrival order
+ * while their device state fits the memory budget and the resident cap; a
+ * request's systems take slots in server-wide pools, one per body count, so
+ * the systems of many small requests fill the same tiles.  Each quantum
+ * advances the scheduled requests' systems by up to steps_per_quantum steps
+ * in one fused launch: every resident request (FB_POLICY_FAIR), or those
+ * with at least long_steps steps left plus, least remaining work first,
+ * others until about quantum_tiles tiles are scheduled (FB_POLICY_SRPT).  Finished requests are copied back and their
+ * memory is reused.  For a fixed plan table a request's results do not
+ * depend on what else is resident or on the schedule.  (No counterpart in
+ * the paper, whose host only sets up, loads, calls and examines -- Section
+ * 5.3; this is the serving form of its many steps per kernel call.) */
 typedef struct fb_server fb_server;
 
 enum { FB_REQ_QUEUED = 0, FB_REQ_RUNNING = 1, FB_REQ_DONE = 2, FB_REQ_CANCELLED = 3,
        FB_REQ_FAILED = 4 };
 
+enum { FB_POLICY_FAIR = 0, FB_POLICY_SRPT = 1 };
+
 typedef struct {
     size_t budget_bytes;        /* device memory for resident requests, allocated
                                    once at creation (0: 4 GiB)                      */
     int32_t max_resident;       /* requests resident at once (0: 4096)              */
-    int32_t steps_per_quantum;  /* steps per resident system per quantum (0: 2000)  */
+    int32_t steps_per_quantum;  /* steps per scheduled system per quantum (0: 2000) */
+    int32_t policy;             /* FB_POLICY_FAIR / FB_POLICY_SRPT                  */
+    int32_t quantum_tiles;      /* SRPT: tiles per quantum to schedule, whole
+                                   requests in order of remaining work (0: twice
+                                   the waves the fused launch keeps resident)       */
+    int32_t chunk_slots;        /* systems per pool chunk, multiple of 64 (0: 512)  */
+    int32_t long_steps;         /* SRPT: requests with at least this many steps left
+                                   run in every quantum, whatever their work, since
+                                   their step count alone sets their latency (0: none) */
 } fb_server_opts;
 
 typedef struct {
@@ -269,10 +283,15 @@ void fb_server_opts_default(fb_server_opts *o);
  * whole budget up front; FB_E_NOMEM if that fails. */
 fb_status fb_server_create(const fb_server_opts *o, void *hip_stream, fb_server **out);
 
+/* Device bytes a request of these body counts needs on an empty server
+ * with options o (NULL: defaults): its staging block plus whole pool chunks
+ * for each body count.  0 on invalid input. */
+size_t fb_server_request_bytes(const fb_server_opts *o, int32_t n_sys, const int32_t *n_body);
+
 /* Queue a request; the host arrays are copied before the call returns
  * (layout as fb_ensemble_create, t0 = 0).  Integrates every system to t_end
  * with fixed step dt.  *req_id identifies it.  FB_E_INVAL on bad input,
- * FB_E_BUDGET if its state alone exceeds the budget. */
+ * FB_E_BUDGET if it would not fit the budget even on an empty server. */
 fb_status fb_server_submit(fb_server *s, int32_t n_sys, const int32_t *n_body,
                            const double *mass, const double *pos, const double *vel,
                            double t_end, double dt, int64_t *req_id);

@@ -74,9 +74,11 @@ inline int tile_systems(int mapping, int n) {
 }
 
 // ---- launchers (fb_kernels.hip) -------------------------------------------
+// pad_tail: also initialise slots count..pitch-1 as inert padding (a whole
+// bucket); false for a view of a bucket shared with other owners.
 hipError_t launch_pack(const Bucket &B, const double *mass, const double *pos,
                        const double *vel, const double *t0,
-                       const long long *orig_off, int *bad, hipStream_t s);
+                       const long long *orig_off, int *bad, bool pad_tail, hipStream_t s);
 hipError_t launch_prepare(const Bucket &B, hipStream_t s);
 hipError_t launch_begin_run(const Bucket &B, int fixed_steps, long long n_steps,
                             double t_end, double dt, int adaptive, double eta,

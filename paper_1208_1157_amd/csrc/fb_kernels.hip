@@ -1064,10 +1064,10 @@ __global__ void k_fill_int(int *p, int n, int value)
 // AoS (caller order) -> bucket SoA; validates the inputs.
 __global__ void k_pack(Bucket B, const double *__restrict__ mass, const double *__restrict__ pos,
                        const double *__restrict__ vel, const double *__restrict__ t0,
-                       const long long *__restrict__ orig_off, int *bad)
+                       const long long *__restrict__ orig_off, int *bad, int limit)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= B.pitch)
+    if (s >= limit)
         return;
     const size_t pitch = B.pitch;
     const int n = B.n;
@@ -1294,12 +1294,13 @@ inline dim3 grid_for(int n, int block) { return dim3((unsigned)((n + block - 1) 
 
 hipError_t launch_pack(const Bucket &B, const double *mass, const double *pos,
                        const double *vel, const double *t0, const long long *orig_off, int *bad,
-                       hipStream_t s)
+                       bool pad_tail, hipStream_t s)
 {
-    if (B.pitch == 0)
+    const int limit = pad_tail ? B.pitch : B.count;
+    if (limit == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_pack, grid_for(B.pitch, 256), dim3(256), 0, s, B, mass, pos, vel, t0,
-                       orig_off, bad);
+    hipLaunchKernelGGL(k_pack, grid_for(limit, 256), dim3(256), 0, s, B, mass, pos, vel, t0,
+                       orig_off, bad, limit);
     return hipGetLastError();
 }
 

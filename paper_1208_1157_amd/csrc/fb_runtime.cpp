@@ -320,7 +320,7 @@ fb_status finish_create(fb_ensemble *e, const double *d_mass, const double *d_po
         return st;
     FB_HIP(launch_reset_counter(e->d_ints, 64, e->stream));
     for (const Bucket &B : e->buckets)
-        FB_HIP(launch_pack(B, d_mass, d_pos, d_vel, d_t0, e->d_orig_off, e->d_ints, e->stream));
+        FB_HIP(launch_pack(B, d_mass, d_pos, d_vel, d_t0, e->d_orig_off, e->d_ints, true, e->stream));
     for (const Bucket &B : e->buckets)
         FB_HIP(launch_prepare(B, e->stream));
     FB_HIP(hipMemcpyAsync(e->h_pinned, e->d_ints, sizeof(int), hipMemcpyDeviceToHost, e->stream));

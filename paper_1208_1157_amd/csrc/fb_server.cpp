@@ -4,21 +4,28 @@
 // queued by fb_server_submit from any thread.  One worker thread owns the
 // GPU work and loops over quanta:
 //   1. admit queued requests in arrival order while their device state fits
-//      the memory budget (a first-fit arena carved from one allocation made
-//      at creation) and the resident-request cap; upload, pack into bucket
-//      SoA and run the set-up evaluation on the device;
-//   2. one fused persistent launch advances every resident system by at
-//      most steps_per_quantum steps (tiles never mix requests, largest work
-//      first);
+//      the memory budget and the resident-request cap.  A request's systems
+//      take free slots in the server-wide pool of their body count: chunks of
+//      chunk_slots systems, each a bucket in the SoA layout, carved from one
+//      allocation made at creation and returned when empty.  Its inputs are
+//      uploaded, packed into those slots, and the set-up evaluation runs;
+//   2. choose the requests this quantum advances (every resident one, or the
+//      least remaining work first until the device is full), list their
+//      slots chunk by chunk and cut the lists into tiles, so a tile holds
+//      systems of several requests and stays full however small each request
+//      is.  One fused persistent launch advances every listed system by at
+//      most steps_per_quantum steps, costliest tiles first;
 //   3. requests whose step count is reached are unpacked and copied back,
 //      their completion time is stamped after the quantum's synchronisation,
-//      and their arena blocks are released for the next admissions.
-// A request that arrives while others run joins at the next quantum, so
-// their work overlaps on the device; its own arithmetic does not depend on
-// what else is resident.
+//      and their slots and memory are released for the next admissions.
+// A system's arithmetic depends only on its own state and on the kernel
+// mapping its body count gets (fixed by the plan table), never on its slot,
+// its tile, its neighbours or how its steps fall into quanta, so each
+// request's results are the same alone and in any mix.
 #include "fb_runtime_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -100,22 +107,122 @@ private:
     std::map<size_t, size_t> free_;
 };
 
+// Device bytes of a pool chunk of `slots` systems of n bodies: the state rows
+// and the per-system clock arrays, each 256-aligned.
+size_t chunk_bytes(int n, int slots)
+{
+    const size_t P = (size_t)slots;
+    return align_up(sizeof(double) * R_COUNT * n * P, 256) + 8 * align_up(8 * P, 256) +
+           2 * align_up(4 * P, 256);
+}
+
+Bucket chunk_bucket(char *base, int n, int slots)
+{
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + o;
+        o += align_up(bytes, 256);
+        return p;
+    };
+    const size_t P = (size_t)slots;
+    Bucket B;
+    B.st = reinterpret_cast<double *>(take(sizeof(double) * R_COUNT * n * P));
+    B.t = reinterpret_cast<double *>(take(8 * P));
+    B.t_end = reinterpret_cast<double *>(take(8 * P));
+    B.dt = reinterpret_cast<double *>(take(8 * P));
+    B.dtn = reinterpret_cast<double *>(take(8 * P));
+    B.t0run = reinterpret_cast<double *>(take(8 * P));
+    B.krun = reinterpret_cast<long long *>(take(8 * P));
+    B.nfull = reinterpret_cast<long long *>(take(8 * P));
+    B.steps = reinterpret_cast<long long *>(take(8 * P));
+    B.status = reinterpret_cast<int *>(take(4 * P));
+    B.orig = reinterpret_cast<int *>(take(4 * P));
+    B.n = n;
+    B.pitch = slots;
+    B.count = slots;
+    B.pad = 0;
+    return B;
+}
+
+// Slots first..first+count-1 of B as a bucket of their own: every per-slot
+// array starts at `first`; the pitch (row stride) stays B's.
+Bucket sub_view(const Bucket &B, int first, int count)
+{
+    Bucket v = B;
+    v.st += first;
+    v.t += first;
+    v.t_end += first;
+    v.dt += first;
+    v.dtn += first;
+    v.t0run += first;
+    v.krun += first;
+    v.nfull += first;
+    v.steps += first;
+    v.status += first;
+    v.orig += first;
+    v.count = count;
+    return v;
+}
+
+// One chunk of a body-count pool, shared by the requests whose systems it
+// holds.
+struct Chunk {
+    int n = 0;
+    size_t off = 0, bytes = 0;
+    Bucket B;                   // every slot: count == pitch
+    std::map<int, int> free;    // free slot runs: first slot -> length
+    int used = 0;
+    int qidx = -1;              // index in the current quantum's bucket table
+};
+
+// A run of one request's slots in a chunk.
+struct Piece {
+    Chunk *c = nullptr;
+    int first = 0, count = 0;
+    std::vector<int> orig;      // caller's index of the system in each slot
+    Bucket view() const { return sub_view(c->B, first, count); }
+};
+
+// Per-request device block: system offsets, and staging for the uploaded
+// inputs (mass, pos, vel) and, later, the results (pos, vel, t, steps,
+// status).
+struct AuxLayout {
+    size_t off_idx = 0, staging = 0, flag = 0, total = 0;
+};
+
+AuxLayout aux_layout(int64_t ns, int64_t N)
+{
+    AuxLayout A;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + std::max<size_t>(bytes, 1), 256);
+        return r;
+    };
+    A.off_idx = take(8 * (size_t)(ns + 1));
+    A.staging = take(8 * (size_t)std::max<int64_t>(7 * N, 6 * N + 2 * ns) + 4 * (size_t)ns);
+    A.flag = take(64);
+    A.total = o;
+    return A;
+}
+
 struct Request {
     int64_t id = 0;
     int32_t n_sys = 0;
     int64_t n_bodies = 0;
     std::vector<int32_t> n_body;
     std::vector<double> mass, pos, vel;
+    std::array<int, kMaxBodies + 1> cnt{};
     double t_end = 0.0, dt = 0.0;
     int state = FB_REQ_QUEUED;
     bool cancel = false;
-    Layout L;
-    size_t arena_off = 0;
-    bool has_block = false;
-    std::vector<Bucket> buckets;
+    AuxLayout aux;
+    size_t aux_off = 0;
+    bool has_aux = false;
+    std::vector<Piece> pieces;
     std::vector<long long> off;
-    std::vector<std::vector<int>> origins;
     long long total_steps = 0, done_steps = 0;
+    double flops_per_step = 0.0;   // all its systems, one step each
     double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
     std::vector<double> out_pos, out_vel, out_t;
     std::vector<int32_t> out_status;
@@ -140,6 +247,23 @@ long long schedule_steps(double t0, double t_end, double dt)
 
 double flops_per_system_step(int n) { return 116.0 * n * (n - 1) / 2 + 120.0 * n; }
 
+// Relative duration of one step of a tile: a system-per-lane lane walks all
+// n(n-1)/2 pairs, a body-per-lane lane its n-1 partners.
+double tile_step_cost(int map, int n)
+{
+    return map == MAP_SPL ? 0.5 * n * (n - 1) + n : (double)n;
+}
+
+// Device bytes a request needs on an empty server.
+size_t request_bytes(const std::array<int, kMaxBodies + 1> &cnt, int64_t ns, int64_t N, int slots)
+{
+    size_t b = align_up(aux_layout(ns, N).total, 256);
+    for (int n = 2; n <= kMaxBodies; ++n)
+        if (cnt[n])
+            b += (size_t)((cnt[n] + slots - 1) / slots) * align_up(chunk_bytes(n, slots), 256);
+    return b;
+}
+
 }  // namespace
 
 struct fb_server {
@@ -150,13 +274,17 @@ struct fb_server {
     bool own_stream = false;
     char *d_arena = nullptr;
     Arena arena;
+    std::vector<std::unique_ptr<Chunk>> pool[kMaxBodies + 1];
     Bucket *d_buckets = nullptr;
     int cap_buckets = 0;
     Tile *d_tiles = nullptr;
     int cap_tiles = 0;
-    int *d_ints = nullptr;   // [0] ntiles, [1] head, [2] scratch flag
+    int *d_list = nullptr;
+    size_t cap_list = 0;
+    int *d_ints = nullptr;   // [0] ntiles, [1] head
     std::vector<Bucket> h_buckets;
     std::vector<Tile> h_tiles;
+    std::vector<int> h_list;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -173,35 +301,152 @@ struct fb_server {
 
 namespace {
 
+// Return a request's slots to their chunks, and empty chunks to the arena.
+void release_pieces(fb_server *S, std::vector<Piece> &pieces)
+{
+    for (Piece &p : pieces) {
+        Chunk *c = p.c;
+        auto it = c->free.emplace(p.first, p.count).first;
+        auto nx = std::next(it);
+        if (nx != c->free.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            c->free.erase(nx);
+        }
+        if (it != c->free.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                c->free.erase(it);
+            }
+        }
+        c->used -= p.count;
+        if (c->used == 0) {
+            S->arena.release(c->off, c->bytes);
+            auto &pool = S->pool[c->n];
+            pool.erase(std::find_if(pool.begin(), pool.end(),
+                                    [c](const std::unique_ptr<Chunk> &q) { return q.get() == c; }));
+        }
+    }
+    pieces.clear();
+}
+
+// k slots of the n-body pool: one free run that holds them all if there is
+// one (first fit), else the free runs in chunk order, else new chunks.
+// false (nothing taken beyond `out`, which the caller releases) when the
+// arena cannot hold another chunk.
+bool alloc_slots(fb_server *S, int n, int k, std::vector<Piece> &out)
+{
+    auto &pool = S->pool[n];
+    auto take = [&](Chunk *c, std::map<int, int>::iterator it, int m) {
+        const int first = it->first, len = it->second;
+        c->free.erase(it);
+        if (len > m)
+            c->free.emplace(first + m, len - m);
+        c->used += m;
+        Piece p;
+        p.c = c;
+        p.first = first;
+        p.count = m;
+        out.push_back(std::move(p));
+    };
+    for (auto &cp : pool)
+        for (auto it = cp->free.begin(); it != cp->free.end(); ++it)
+            if (it->second >= k) {
+                take(cp.get(), it, k);
+                return true;
+            }
+    for (auto &cp : pool) {
+        while (k > 0 && !cp->free.empty()) {
+            const int m = std::min(k, cp->free.begin()->second);
+            take(cp.get(), cp->free.begin(), m);
+            k -= m;
+        }
+        if (k == 0)
+            return true;
+    }
+    const int slots = S->opts.chunk_slots;
+    while (k > 0) {
+        std::unique_ptr<Chunk> c(new Chunk());
+        c->n = n;
+        c->bytes = chunk_bytes(n, slots);
+        if (!S->arena.alloc(c->bytes, c->off))
+            return false;
+        c->B = chunk_bucket(S->arena.base() + c->off, n, slots);
+        c->free.emplace(0, slots);
+        Chunk *raw = c.get();
+        pool.push_back(std::move(c));
+        const int m = std::min(k, slots);
+        take(raw, raw->free.begin(), m);
+        k -= m;
+    }
+    return true;
+}
+
+// Memory for a queued request: its aux block and slots for all its systems.
+// On failure everything taken is given back.
+bool reserve(fb_server *S, Request *R)
+{
+    if (!S->arena.alloc(R->aux.total, R->aux_off))
+        return false;
+    R->has_aux = true;
+    std::vector<std::vector<int>> by_n(kMaxBodies + 1);
+    for (int s = 0; s < R->n_sys; ++s)
+        by_n[R->n_body[s]].push_back(s);
+    for (int n = kMaxBodies; n >= 2; --n) {
+        if (by_n[n].empty())
+            continue;
+        const size_t before = R->pieces.size();
+        if (!alloc_slots(S, n, (int)by_n[n].size(), R->pieces)) {
+            release_pieces(S, R->pieces);
+            S->arena.release(R->aux_off, R->aux.total);
+            R->has_aux = false;
+            return false;
+        }
+        size_t k = 0;
+        for (size_t i = before; i < R->pieces.size(); ++i) {
+            Piece &p = R->pieces[i];
+            p.orig.assign(by_n[n].begin() + k, by_n[n].begin() + k + p.count);
+            k += p.count;
+        }
+    }
+    return true;
+}
+
+void release_request(fb_server *S, Request *R)
+{
+    release_pieces(S, R->pieces);
+    if (R->has_aux) {
+        S->arena.release(R->aux_off, R->aux.total);
+        R->has_aux = false;
+    }
+}
+
 fb_status admit_one(fb_server *S, Request *R)
 {
-    char *base = S->arena.base() + R->arena_off;
-    R->buckets = bucket_views(base, R->L);
+    char *aux = S->arena.base() + R->aux_off;
     const int ns = R->n_sys;
     const size_t N = (size_t)R->n_bodies;
     R->off.assign(ns + 1, 0);
     for (int s = 0; s < ns; ++s)
         R->off[s + 1] = R->off[s] + R->n_body[s];
-    long long *d_off = reinterpret_cast<long long *>(base + R->L.orig_off);
-    double *stg = reinterpret_cast<double *>(base + R->L.staging);
-    int *d_flag = reinterpret_cast<int *>(base + R->L.ints);
+    long long *d_off = reinterpret_cast<long long *>(aux + R->aux.off_idx);
+    double *stg = reinterpret_cast<double *>(aux + R->aux.staging);
+    int *d_flag = reinterpret_cast<int *>(aux + R->aux.flag);
     FB_HIP(hipMemcpyAsync(d_off, R->off.data(), sizeof(long long) * (ns + 1), hipMemcpyHostToDevice,
                           S->stream));
-    FB_HIP(hipMemcpyAsync(stg, R->mass.data(), 8 * N, hipMemcpyHostToDevice, S->stream));
-    FB_HIP(hipMemcpyAsync(stg + N, R->pos.data(), 24 * N, hipMemcpyHostToDevice, S->stream));
-    FB_HIP(hipMemcpyAsync(stg + 4 * N, R->vel.data(), 24 * N, hipMemcpyHostToDevice, S->stream));
-    R->origins.clear();
-    for (const Bucket &B : R->buckets) {
-        R->origins.push_back(slot_origins(R->n_body, B));
-        FB_HIP(hipMemcpyAsync(B.orig, R->origins.back().data(), sizeof(int) * B.pitch,
-                              hipMemcpyHostToDevice, S->stream));
+    if (N) {
+        FB_HIP(hipMemcpyAsync(stg, R->mass.data(), 8 * N, hipMemcpyHostToDevice, S->stream));
+        FB_HIP(hipMemcpyAsync(stg + N, R->pos.data(), 24 * N, hipMemcpyHostToDevice, S->stream));
+        FB_HIP(hipMemcpyAsync(stg + 4 * N, R->vel.data(), 24 * N, hipMemcpyHostToDevice, S->stream));
     }
-    for (const Bucket &B : R->buckets)
-        FB_HIP(launch_pack(B, stg, stg + N, stg + 4 * N, nullptr, d_off, d_flag, S->stream));
-    for (const Bucket &B : R->buckets)
-        FB_HIP(launch_prepare(B, S->stream));
-    for (const Bucket &B : R->buckets)
-        FB_HIP(launch_begin_run(B, 0, 0, R->t_end, R->dt, 0, 0.0, S->stream));
+    for (const Piece &p : R->pieces) {
+        const Bucket V = p.view();
+        FB_HIP(hipMemcpyAsync(V.orig, p.orig.data(), sizeof(int) * p.count, hipMemcpyHostToDevice,
+                              S->stream));
+        FB_HIP(launch_pack(V, stg, stg + N, stg + 4 * N, nullptr, d_off, d_flag, false, S->stream));
+        FB_HIP(launch_prepare(V, S->stream));
+        FB_HIP(launch_begin_run(V, 0, 0, R->t_end, R->dt, 0, 0.0, S->stream));
+    }
     R->total_steps = schedule_steps(0.0, R->t_end, R->dt);
     R->done_steps = 0;
     return FB_OK;
@@ -209,16 +454,16 @@ fb_status admit_one(fb_server *S, Request *R)
 
 fb_status finish_one(fb_server *S, Request *R)
 {
-    char *base = S->arena.base() + R->arena_off;
+    char *aux = S->arena.base() + R->aux_off;
     const size_t N = (size_t)R->n_bodies, ns = (size_t)R->n_sys;
-    const long long *d_off = reinterpret_cast<const long long *>(base + R->L.orig_off);
-    double *stg = reinterpret_cast<double *>(base + R->L.staging);
+    const long long *d_off = reinterpret_cast<const long long *>(aux + R->aux.off_idx);
+    double *stg = reinterpret_cast<double *>(aux + R->aux.staging);
     double *d_pos = stg, *d_vel = stg + 3 * N, *d_t = stg + 6 * N;
     long long *d_steps = reinterpret_cast<long long *>(d_t + ns);
     int *d_status = reinterpret_cast<int *>(d_steps + ns);
-    for (const Bucket &B : R->buckets)
-        FB_HIP(launch_unpack(B, d_off, d_pos, d_vel, nullptr, nullptr, d_t, d_status, d_steps,
-                             nullptr, S->stream));
+    for (const Piece &p : R->pieces)
+        FB_HIP(launch_unpack(p.view(), d_off, d_pos, d_vel, nullptr, nullptr, d_t, d_status,
+                             d_steps, nullptr, S->stream));
     R->out_pos.resize(3 * N);
     R->out_vel.resize(3 * N);
     R->out_t.resize(ns);
@@ -238,59 +483,144 @@ fb_status finish_one(fb_server *S, Request *R)
     return FB_OK;
 }
 
-fb_status ensure_capacity(fb_server *S, int nb, int nt)
+template <class T>
+fb_status grow(T *&p, size_t &cap, size_t need)
 {
-    if (nb > S->cap_buckets) {
-        if (S->d_buckets)
-            FB_HIP(hipFree(S->d_buckets));
-        S->cap_buckets = std::max(nb, 2 * S->cap_buckets);
-        FB_HIP(hipMalloc((void **)&S->d_buckets, sizeof(Bucket) * S->cap_buckets));
-    }
-    if (nt > S->cap_tiles) {
-        if (S->d_tiles)
-            FB_HIP(hipFree(S->d_tiles));
-        S->cap_tiles = std::max(nt, 2 * S->cap_tiles);
-        FB_HIP(hipMalloc((void **)&S->d_tiles, sizeof(Tile) * S->cap_tiles));
-    }
+    if (need <= cap)
+        return FB_OK;
+    if (p)
+        FB_HIP(hipFree(p));
+    p = nullptr;
+    cap = std::max(need, 2 * cap);
+    FB_HIP(hipMalloc((void **)&p, sizeof(T) * cap));
     return FB_OK;
 }
 
-// One quantum over every resident request.  Returns the requests it finished.
+// Fused-kernel mapping of body count n under class cls.
+int server_mapping(int cls, int n)
+{
+    const int lim = persistent_spl_limit(cls, 0);
+    return (n <= lim && (get_plan(n).mapping == MAP_SPL || cls == 1)) ? MAP_SPL : MAP_BPL;
+}
+
+// One quantum.  Returns the requests it finished (reached their step count
+// or were cancelled).
 fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sys_steps)
 {
     const int Q = S->opts.steps_per_quantum;
-    struct Item {
-        Tile t;
-        double cost;
-    };
-    std::vector<Item> items;
-    S->h_buckets.clear();
     sys_steps = 0.0;
     // The fused-kernel class is fixed by the plan (auto: body-per-lane), never
     // by the resident mix, so every request sees the same arithmetic alone
     // and among others.
     const Plan p0 = get_plan(0);
     const int cls = p0.mapping == MAP_SPL ? 1 : 0;
-    const int spl_lim = persistent_spl_limit(cls, 0);
+    const int W = std::max(1, std::min(4, p0.waves_per_group));
+    int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
+    const int occ = persistent_max_groups_per_cu(0, cls, W);
+    if (occ > 0)
+        gpc = std::min(gpc, occ);
+
+    std::vector<Request *> live;
     for (Request *R : S->resident) {
-        const long long left = R->total_steps - R->done_steps;
-        const long long adv = std::min<long long>(left, Q);
-        sys_steps += (double)R->n_sys * (double)adv;
-        for (const Bucket &B : R->buckets) {
-            const int bi = (int)S->h_buckets.size();
-            S->h_buckets.push_back(B);
-            const Plan p = get_plan(B.n);
-            const int map = (B.n <= spl_lim && (p.mapping == MAP_SPL || cls == 1)) ? MAP_SPL : MAP_BPL;
-            const int cap = tile_systems(map, B.n);
-            for (int f = 0; f < B.count; f += cap) {
-                Item it;
-                it.t.bucket = bi;
-                it.t.first = f;
-                it.t.count = std::min(cap, B.count - f);
-                it.t.kind = map * 32 + B.n;
-                it.cost = (double)it.t.count * flops_per_system_step(B.n) * (double)adv;
-                items.push_back(it);
+        if (R->cancel || R->done_steps >= R->total_steps)
+            finished.push_back(R);
+        else
+            live.push_back(R);
+    }
+    // Requests this quantum advances.
+    std::vector<Request *> sched;
+    if (S->opts.policy == FB_POLICY_SRPT) {
+        std::stable_sort(live.begin(), live.end(), [](const Request *a, const Request *b) {
+            return (double)(a->total_steps - a->done_steps) * a->flops_per_step <
+                   (double)(b->total_steps - b->done_steps) * b->flops_per_step;
+        });
+        const long long target = S->opts.quantum_tiles > 0
+                                     ? S->opts.quantum_tiles
+                                     : 2LL * gpc * W * S->num_cu;
+        auto tiles_of = [&](const Request *R) {
+            long long t = 0;
+            for (int n = 2; n <= kMaxBodies; ++n)
+                if (R->cnt[n]) {
+                    const int cap = tile_systems(server_mapping(cls, n), n);
+                    t += (R->cnt[n] + cap - 1) / cap;
+                }
+            return t;
+        };
+        const long long L = S->opts.long_steps;
+        long long tiles = 0;
+        std::vector<Request *> rest;
+        for (Request *R : live) {
+            if (L > 0 && R->total_steps - R->done_steps >= L) {
+                sched.push_back(R);
+                tiles += tiles_of(R);
+            } else {
+                rest.push_back(R);
             }
+        }
+        for (Request *R : rest) {
+            if (tiles >= target)
+                break;
+            sched.push_back(R);
+            tiles += tiles_of(R);
+        }
+    } else {
+        sched = live;
+    }
+
+    // Slot runs of the scheduled requests, grouped by chunk (largest n
+    // first) and, inside a chunk, by steps left this quantum so that a tile's
+    // lanes finish together.
+    struct Run {
+        Chunk *c;
+        int first, count;
+        long long adv;
+    };
+    std::vector<Run> runs;
+    for (Request *R : sched) {
+        const long long adv = std::min<long long>(R->total_steps - R->done_steps, Q);
+        sys_steps += (double)R->n_sys * (double)adv;
+        for (const Piece &p : R->pieces)
+            runs.push_back({p.c, p.first, p.count, adv});
+    }
+    std::sort(runs.begin(), runs.end(), [](const Run &a, const Run &b) {
+        if (a.c->n != b.c->n)
+            return a.c->n > b.c->n;
+        if (a.c != b.c)
+            return a.c < b.c;
+        if (a.adv != b.adv)
+            return a.adv > b.adv;
+        return a.first < b.first;
+    });
+    struct Item {
+        Tile t;
+        double cost;
+    };
+    std::vector<Item> items;
+    S->h_buckets.clear();
+    S->h_list.clear();
+    for (size_t i = 0; i < runs.size();) {
+        Chunk *c = runs[i].c;
+        const int n = c->n;
+        const int map = server_mapping(cls, n);
+        const int cap = tile_systems(map, n);
+        const int bi = (int)S->h_buckets.size();
+        S->h_buckets.push_back(c->B);
+        const size_t list0 = S->h_list.size();
+        std::vector<long long> adv_of;
+        for (; i < runs.size() && runs[i].c == c; ++i)
+            for (int k = 0; k < runs[i].count; ++k) {
+                S->h_list.push_back(runs[i].first + k);
+                adv_of.push_back(runs[i].adv);
+            }
+        const size_t len = S->h_list.size() - list0;
+        for (size_t f = 0; f < len; f += cap) {
+            Item it;
+            it.t.bucket = bi;
+            it.t.first = (int)(list0 + f);
+            it.t.count = (int)std::min<size_t>(cap, len - f);
+            it.t.kind = map * 32 + n;
+            it.cost = (double)adv_of[f] * tile_step_cost(map, n);   // adv_of is non-increasing
+            items.push_back(it);
         }
     }
     std::stable_sort(items.begin(), items.end(),
@@ -299,7 +629,14 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
     for (const Item &it : items)
         S->h_tiles.push_back(it.t);
     const int nb = (int)S->h_buckets.size(), nt = (int)S->h_tiles.size();
-    fb_status stc = ensure_capacity(S, nb, nt);
+    size_t cb = (size_t)S->cap_buckets, ct = (size_t)S->cap_tiles;
+    fb_status stc = grow(S->d_buckets, cb, (size_t)nb);
+    if (stc == FB_OK)
+        stc = grow(S->d_tiles, ct, (size_t)nt);
+    if (stc == FB_OK)
+        stc = grow(S->d_list, S->cap_list, S->h_list.size());
+    S->cap_buckets = (int)cb;
+    S->cap_tiles = (int)ct;
     if (stc != FB_OK)
         return stc;
     int ints[2] = {nt, 0};   // must outlive the asynchronous copy (synchronised below)
@@ -307,6 +644,8 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
         FB_HIP(hipMemcpyAsync(S->d_buckets, S->h_buckets.data(), sizeof(Bucket) * nb,
                               hipMemcpyHostToDevice, S->stream));
         FB_HIP(hipMemcpyAsync(S->d_tiles, S->h_tiles.data(), sizeof(Tile) * nt,
+                              hipMemcpyHostToDevice, S->stream));
+        FB_HIP(hipMemcpyAsync(S->d_list, S->h_list.data(), sizeof(int) * S->h_list.size(),
                               hipMemcpyHostToDevice, S->stream));
         FB_HIP(hipMemcpyAsync(S->d_ints, ints, sizeof ints, hipMemcpyHostToDevice, S->stream));
         StepParams P;
@@ -317,19 +656,14 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
         P.max_steps = LLONG_MAX;
         P.quantum = Q;
         P.pad = 0;
-        const int W = std::max(1, std::min(4, p0.waves_per_group));
-        int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
-        const int occ = persistent_max_groups_per_cu(0, cls, W);
-        if (occ > 0)
-            gpc = std::min(gpc, occ);
         const int grid = std::max(1, std::min(gpc * S->num_cu, nt));
         ProfScope ps(S->stream);
-        FB_HIP(launch_persistent(S->d_buckets, S->d_tiles, S->d_ints, S->d_ints + 1, nullptr, P, 0,
-                                 cls, grid, W, nullptr, S->stream));
+        FB_HIP(launch_persistent(S->d_buckets, S->d_tiles, S->d_ints, S->d_ints + 1, S->d_list, P,
+                                 0, cls, grid, W, nullptr, S->stream));
     }
-    for (Request *R : S->resident) {
+    for (Request *R : sched) {
         R->done_steps = std::min(R->total_steps, R->done_steps + Q);
-        if (R->done_steps >= R->total_steps || R->cancel)
+        if (R->done_steps >= R->total_steps)
             finished.push_back(R);
     }
     for (Request *R : finished)
@@ -368,11 +702,8 @@ void worker_main(fb_server *S)
             while (!S->queue.empty() &&
                    (int)(S->resident.size() + admitted.size()) < S->opts.max_resident) {
                 Request *R = S->queue.front();
-                size_t off = 0;
-                if (!S->arena.alloc(R->L.total, off))
+                if (!reserve(S, R))
                     break;
-                R->arena_off = off;
-                R->has_block = true;
                 S->queue.pop_front();
                 admitted.push_back(R);
             }
@@ -412,7 +743,7 @@ void worker_main(fb_server *S)
             S->cv_done.notify_all();
             break;
         }
-        if (!S->resident.empty() || !finished.empty()) {
+        if (sys_steps > 0.0 || !finished.empty()) {
             S->st.quanta++;
             S->st.busy_seconds += t1 - t0;
             S->st.system_steps += sys_steps;
@@ -423,8 +754,7 @@ void worker_main(fb_server *S)
             R->state = R->cancel ? FB_REQ_CANCELLED : FB_REQ_DONE;
             if (!R->cancel)
                 S->st.completed++;
-            S->arena.release(R->arena_off, R->L.total);
-            R->has_block = false;
+            release_request(S, R);
             S->resident.erase(std::find(S->resident.begin(), S->resident.end(), R));
         }
         S->st.bytes_in_use = S->arena.used();
@@ -442,6 +772,51 @@ bool finite_all(const double *p, size_t n)
     return true;
 }
 
+// Fill o's zero fields from the defaults and check it.
+fb_status resolve_opts(const fb_server_opts *po, fb_server_opts &o)
+{
+    fb_server_opts_default(&o);
+    if (po) {
+        if (po->budget_bytes)
+            o.budget_bytes = po->budget_bytes;
+        if (po->max_resident)
+            o.max_resident = po->max_resident;
+        if (po->steps_per_quantum)
+            o.steps_per_quantum = po->steps_per_quantum;
+        o.policy = po->policy;
+        o.quantum_tiles = po->quantum_tiles;
+        o.long_steps = po->long_steps;
+        if (po->chunk_slots)
+            o.chunk_slots = po->chunk_slots;
+    }
+    if (o.max_resident < 1 || o.steps_per_quantum < 1 || o.budget_bytes < 4096)
+        return fail(FB_E_INVAL, "max_resident and steps_per_quantum must be >= 1, budget >= 4 KiB");
+    if (o.policy != FB_POLICY_FAIR && o.policy != FB_POLICY_SRPT)
+        return fail(FB_E_INVAL, "policy must be FB_POLICY_FAIR or FB_POLICY_SRPT");
+    if (o.quantum_tiles < 0 || o.long_steps < 0)
+        return fail(FB_E_INVAL, "quantum_tiles and long_steps must be >= 0");
+    if (o.chunk_slots < 64 || o.chunk_slots > (1 << 20) || o.chunk_slots % 64)
+        return fail(FB_E_INVAL, "chunk_slots must be a multiple of 64 in 64..2^20");
+    return FB_OK;
+}
+
+// Body-count histogram of a request; false on a bad count.
+bool count_bodies(int32_t n_sys, const int32_t *n_body, std::array<int, kMaxBodies + 1> &cnt,
+                         int64_t &N)
+{
+    cnt.fill(0);
+    N = 0;
+    if (n_sys < 0 || (n_sys > 0 && !n_body))
+        return false;
+    for (int32_t s = 0; s < n_sys; ++s) {
+        if (n_body[s] < 2 || n_body[s] > kMaxBodies)
+            return false;
+        cnt[n_body[s]]++;
+        N += n_body[s];
+    }
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -454,6 +829,19 @@ void fb_server_opts_default(fb_server_opts *o)
     o->budget_bytes = (size_t)4 << 30;
     o->max_resident = 4096;
     o->steps_per_quantum = 2000;
+    o->policy = FB_POLICY_FAIR;
+    o->quantum_tiles = 0;
+    o->chunk_slots = 512;
+}
+
+size_t fb_server_request_bytes(const fb_server_opts *po, int32_t n_sys, const int32_t *n_body)
+{
+    fb_server_opts o;
+    std::array<int, kMaxBodies + 1> cnt;
+    int64_t N = 0;
+    if (resolve_opts(po, o) != FB_OK || !count_bodies(n_sys, n_body, cnt, N))
+        return 0;
+    return request_bytes(cnt, n_sys, N, o.chunk_slots);
 }
 
 double fb_monotonic_seconds(void) { return now_s(); }
@@ -464,17 +852,9 @@ fb_status fb_server_create(const fb_server_opts *po, void *hip_stream, fb_server
         return fail(FB_E_INVAL, "out is NULL");
     *out = nullptr;
     fb_server_opts o;
-    fb_server_opts_default(&o);
-    if (po) {
-        if (po->budget_bytes)
-            o.budget_bytes = po->budget_bytes;
-        if (po->max_resident)
-            o.max_resident = po->max_resident;
-        if (po->steps_per_quantum)
-            o.steps_per_quantum = po->steps_per_quantum;
-    }
-    if (o.max_resident < 1 || o.steps_per_quantum < 1 || o.budget_bytes < 4096)
-        return fail(FB_E_INVAL, "max_resident and steps_per_quantum must be >= 1, budget >= 4 KiB");
+    const fb_status so = resolve_opts(po, o);
+    if (so != FB_OK)
+        return so;
     std::unique_ptr<fb_server> S(new fb_server());
     S->opts = o;
     std::memset(&S->st, 0, sizeof S->st);
@@ -515,9 +895,10 @@ fb_status fb_server_submit(fb_server *S, int32_t n_sys, const int32_t *n_body, c
     if (!S || !req_id)
         return fail(FB_E_INVAL, "server and req_id are required");
     std::unique_ptr<Request> R(new Request());
-    if (!make_layout(n_sys, n_body, R->L))
+    int64_t nbod = 0;
+    if (!count_bodies(n_sys, n_body, R->cnt, nbod))
         return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxBodies);
-    const size_t N = (size_t)R->L.n_bodies;
+    const size_t N = (size_t)nbod;
     if (N && (!mass || !pos || !vel))
         return fail(FB_E_INVAL, "mass, pos and vel are required");
     for (size_t i = 0; i < N; ++i)
@@ -527,9 +908,13 @@ fb_status fb_server_submit(fb_server *S, int32_t n_sys, const int32_t *n_body, c
         return fail(FB_E_INVAL, "pos and vel must be finite");
     if (!(std::isfinite(t_end) && std::isfinite(dt) && dt != 0.0))
         return fail(FB_E_INVAL, "t_end must be finite and dt finite and non-zero");
-    if (align_up(R->L.total, 256) > S->opts.budget_bytes)
-        return fail(FB_E_BUDGET, "request needs %zu bytes of device state, budget is %zu",
-                    R->L.total, S->opts.budget_bytes);
+    const size_t need = request_bytes(R->cnt, n_sys, nbod, S->opts.chunk_slots);
+    if (need > S->opts.budget_bytes)
+        return fail(FB_E_BUDGET, "request needs %zu bytes of device memory, budget is %zu", need,
+                    S->opts.budget_bytes);
+    R->aux = aux_layout(n_sys, nbod);
+    for (int n = 2; n <= kMaxBodies; ++n)
+        R->flops_per_step += R->cnt[n] * flops_per_system_step(n);
     R->n_sys = n_sys;
     R->n_bodies = (int64_t)N;
     R->n_body.assign(n_body, n_body + n_sys);
@@ -662,6 +1047,8 @@ fb_status fb_server_destroy(fb_server *S)
     (void)hipStreamSynchronize(S->stream);
     if (S->d_tiles)
         (void)hipFree(S->d_tiles);
+    if (S->d_list)
+        (void)hipFree(S->d_list);
     if (S->d_buckets)
         (void)hipFree(S->d_buckets);
     if (S->d_ints)

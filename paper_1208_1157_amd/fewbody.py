@@ -46,7 +46,9 @@ class FbOpts(ctypes.Structure):
 
 class FbServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_resident", ctypes.c_int32),
-                ("steps_per_quantum", ctypes.c_int32)]
+                ("steps_per_quantum", ctypes.c_int32), ("policy", ctypes.c_int32),
+                ("quantum_tiles", ctypes.c_int32), ("chunk_slots", ctypes.c_int32),
+                ("long_steps", ctypes.c_int32)]
 
 
 class FbServerStats(ctypes.Structure):
@@ -64,6 +66,7 @@ class FbTuneEntry(ctypes.Structure):
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = range(5)
+POLICY_FAIR, POLICY_SRPT = 0, 1
 
 _p = ctypes.c_void_p
 _i32, _i64, _d, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -88,6 +91,7 @@ _SIGS = {
     "fb_profile_read": (ctypes.c_int, [_p, _p]),
     "fb_server_opts_default": (None, [ctypes.POINTER(FbServerOpts)]),
     "fb_server_create": (ctypes.c_int, [ctypes.POINTER(FbServerOpts), _p, ctypes.POINTER(_p)]),
+    "fb_server_request_bytes": (_sz, [ctypes.POINTER(FbServerOpts), _i32, _p]),
     "fb_server_submit": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p, _d, _d, ctypes.POINTER(_i64)]),
     "fb_server_poll": (ctypes.c_int, [_p, _i64, ctypes.POINTER(_i32)]),
     "fb_server_wait": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(_i32)]),
@@ -299,6 +303,19 @@ def monotonic() -> float:
     return _lib.fb_monotonic_seconds()
 
 
+def server_opts(budget_bytes=0, max_resident=0, steps_per_quantum=0, policy=POLICY_FAIR,
+                quantum_tiles=0, chunk_slots=0, long_steps=0) -> FbServerOpts:
+    return FbServerOpts(int(budget_bytes), int(max_resident), int(steps_per_quantum), int(policy),
+                        int(quantum_tiles), int(chunk_slots), int(long_steps))
+
+
+def server_request_bytes(n_body, **opts) -> int:
+    """Device bytes a request of these body counts needs on an empty server."""
+    nb = np.ascontiguousarray(n_body, dtype=np.int32)
+    o = server_opts(**opts)
+    return int(_lib.fb_server_request_bytes(ctypes.byref(o), int(nb.shape[0]), _ptr(nb)))
+
+
 class Server:
     """Continuous-batching integration server (fb_server_*).
 
@@ -307,8 +324,10 @@ class Server:
     and resident cap, advances every resident system in fused quanta, and
     retires finished requests."""
 
-    def __init__(self, budget_bytes=0, max_resident=0, steps_per_quantum=0, stream=None):
-        o = FbServerOpts(int(budget_bytes), int(max_resident), int(steps_per_quantum))
+    def __init__(self, budget_bytes=0, max_resident=0, steps_per_quantum=0, stream=None,
+                 policy=POLICY_FAIR, quantum_tiles=0, chunk_slots=0, long_steps=0):
+        o = server_opts(budget_bytes, max_resident, steps_per_quantum, policy, quantum_tiles,
+                        chunk_slots, long_steps)
         self._h = ctypes.c_void_p()
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(_lib.fb_server_create(ctypes.byref(o), sp, ctypes.byref(self._h)))

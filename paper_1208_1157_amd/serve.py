@@ -35,9 +35,10 @@ def request_steps(t_end, dt):
 
 
 def run_trace(fb, trace, budget_bytes=0, max_resident=0, steps_per_quantum=0, keep_results=False,
-              log=None):
+              log=None, policy=0, quantum_tiles=0, chunk_slots=0, long_steps=0):
     """Replay `trace` (list of gen.Request) in real time; returns a report dict."""
-    srv = fb.Server(budget_bytes, max_resident, steps_per_quantum)
+    srv = fb.Server(budget_bytes, max_resident, steps_per_quantum, policy=policy,
+                    quantum_tiles=quantum_tiles, chunk_slots=chunk_slots, long_steps=long_steps)
     try:
         t0 = fb.monotonic()
         ids = []

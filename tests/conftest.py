@@ -28,3 +28,12 @@ def fb():
         pytest.skip("no GPU")
     from paper_1208_1157_amd import fewbody
     return fewbody
+
+
+@pytest.fixture
+def plans(fb):
+    """The library's plan table, restored after the test."""
+    saved = {n: fb.get_plan(n) for n in [0] + list(range(2, 17))}
+    yield fb
+    for n, (m, w, g) in saved.items():
+        fb.set_plan(n, m, w, g)

@@ -110,3 +110,22 @@ def test_product_path_does_not_touch_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt and "hermite_oracle" not in txt, f
+
+
+def test_server_request_bytes(fbmod):
+    """Host-only accounting: a staging block plus whole pool chunks per body
+    count; invalid counts or options give 0."""
+    assert ctypes.sizeof(fbmod.FbServerOpts) == 32
+    one = fbmod.server_request_bytes([5], chunk_slots=64)
+    full = fbmod.server_request_bytes([5] * 64, chunk_slots=64)
+    two_chunks = fbmod.server_request_bytes([5] * 65, chunk_slots=64)
+    two_counts = fbmod.server_request_bytes([5, 6], chunk_slots=64)
+    assert 0 < one < full < two_chunks
+    assert two_counts > one
+    assert fbmod.server_request_bytes([5] * 64) > full          # default chunks hold 512
+    assert fbmod.server_request_bytes([1], chunk_slots=64) == 0
+    assert fbmod.server_request_bytes([17]) == 0
+    assert fbmod.server_request_bytes([5], chunk_slots=100) == 0  # not a multiple of 64
+    assert fbmod.server_request_bytes([5], policy=7) == 0
+    assert fbmod.server_request_bytes([5], long_steps=-1) == 0
+    assert fbmod.server_request_bytes([]) > 0

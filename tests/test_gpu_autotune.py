@@ -14,14 +14,6 @@ pytestmark = pytest.mark.gpu
 H = 2 * math.pi / 2000
 
 
-@pytest.fixture
-def plans(fb):
-    saved = {n: fb.get_plan(n) for n in [0] + list(range(2, 17))}
-    yield fb
-    for n, (m, w, g) in saved.items():
-        fb.set_plan(n, m, w, g)
-
-
 def test_autotune_restores_state_and_installs_plans(plans, ora):
     fb = plans
     ens = gen.ragged_hill(600, seed=13, n_lo=3, n_hi=9)

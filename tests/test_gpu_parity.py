@@ -24,14 +24,6 @@ def say(*a):
     print("[case]", *a, file=sys.stderr, flush=True)
 
 
-@pytest.fixture
-def plans(fb):
-    saved = {n: fb.get_plan(n) for n in [0] + list(range(2, 17))}
-    yield fb
-    for n, (m, w, g) in saved.items():
-        fb.set_plan(n, m, w, g)
-
-
 def run_gpu(fb, ens, steps, h, opts=None, host=False):
     E = fb.from_gen(ens, host=host)
     E.integrate_steps(steps, h, opts)

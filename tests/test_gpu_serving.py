@@ -27,10 +27,18 @@ def small_requests(n_req, seed, max_sys=48, orbits=(0.3, 2.5)):
     return out
 
 
-def test_results_identical_alone_and_in_the_mix(fb, ora):
+@pytest.mark.parametrize("cls,policy", [("bpl", 0), ("spl", 0), ("bpl", 1)])
+def test_results_identical_alone_and_in_the_mix(plans, ora, cls, policy):
+    """Systems of all requests share pool chunks and tiles; each request's
+    results are bit-identical alone, in the mix and through an ensemble, in
+    either fused-kernel class and under either scheduling policy."""
+    fb = plans
+    fb.set_plan(0, fb.MAP_SPL if cls == "spl" else fb.MAP_BPL, 2, 8)
     reqs = small_requests(16, seed=1)
-    say("mix of", len(reqs), "requests")
-    with fb.Server(steps_per_quantum=300) as srv:
+    say("mix of", len(reqs), "requests", cls, "policy", policy)
+    kw = dict(steps_per_quantum=300, policy=policy, chunk_slots=64,
+              quantum_tiles=8 if policy == fb.POLICY_SRPT else 0)
+    with fb.Server(**kw) as srv:
         ids = [srv.submit_gen(e, t, H) for e, t in reqs]
         mixed = []
         for rid in ids:
@@ -40,7 +48,7 @@ def test_results_identical_alone_and_in_the_mix(fb, ora):
         assert any(mixed[j]["t_admit"] < mixed[i]["t_done"] for i in range(len(mixed))
                    for j in range(i + 1, len(mixed)))
     for k, (ens, t_end) in enumerate(reqs):
-        with fb.Server(steps_per_quantum=300) as solo:
+        with fb.Server(**kw) as solo:
             rid = solo.submit_gen(ens, t_end, H)
             solo.wait(rid, 60.0)
             alone = solo.result(rid)
@@ -67,11 +75,20 @@ def test_results_identical_alone_and_in_the_mix(fb, ora):
 
 
 def test_admission_by_memory_budget(fb):
-    reqs = small_requests(6, seed=2, max_sys=64, orbits=(1.0, 1.5))
-    need = max(fb.workspace_bytes(e.n_body) for e, _ in reqs)
-    budget = int(2.2 * need)
+    """Requests that each fill a pool chunk cannot share one: with room for a
+    single request, each waits until the one before it finishes."""
+    slots = 64
+    reqs = []
+    for k in range(4):
+        ens = gen.ragged_hill(slots, seed=20 + k, n_lo=5, n_hi=5)
+        reqs.append((ens, 2 * math.pi * (1.0 + 0.1 * k)))
+    need = fb.server_request_bytes(reqs[0][0].n_body, chunk_slots=slots)
+    assert need > 0
+    assert fb.server_request_bytes(reqs[0][0].n_body[:1], chunk_slots=slots) < need
+    assert fb.server_request_bytes([1], chunk_slots=slots) == 0
+    budget = int(1.5 * need)
     say("budget", budget)
-    with fb.Server(budget_bytes=budget, steps_per_quantum=200) as srv:
+    with fb.Server(budget_bytes=budget, steps_per_quantum=200, chunk_slots=slots) as srv:
         ids = [srv.submit_gen(e, t, H) for e, t in reqs]
         res = []
         for rid in ids:
@@ -80,12 +97,33 @@ def test_admission_by_memory_budget(fb):
         st = srv.stats()
         assert st["peak_bytes"] <= budget
         assert st["completed"] == len(reqs)
-    # someone had to wait for memory: admitted after another finished
-    assert any(res[j]["t_admit"] >= res[i]["t_done"] for i in range(len(res)) for j in range(len(res)) if i != j)
-    with fb.Server(budget_bytes=16384) as tiny:
+    for i in range(1, len(res)):
+        assert res[i]["t_admit"] >= res[i - 1]["t_done"], i
+    # the same numbers as an unconstrained server
+    with fb.Server(steps_per_quantum=200, chunk_slots=slots) as big:
+        rid = big.submit_gen(*reqs[2], H)
+        big.wait(rid, 60.0)
+        assert np.array_equal(big.result(rid)["pos"], res[2]["pos"])
+    with fb.Server(budget_bytes=max(4096, need - 256), chunk_slots=slots) as tiny:
         with pytest.raises(fb.FewbodyError) as ei:
             tiny.submit_gen(reqs[0][0], 1.0, H)
         assert ei.value.code == fb.E_BUDGET
+
+
+def test_srpt_runs_least_remaining_work_first(fb):
+    """One quantum holds one request (quantum_tiles = 1): the short requests
+    submitted after a long one still finish before it."""
+    long_ens = gen.ragged_hill(32, seed=30, n_lo=4, n_hi=6)
+    short = [gen.ragged_hill(8, seed=31 + k, n_lo=3, n_hi=5) for k in range(4)]
+    with fb.Server(steps_per_quantum=500, policy=fb.POLICY_SRPT, quantum_tiles=1) as srv:
+        lid = srv.submit_gen(long_ens, 5000 * H, H)
+        sids = [srv.submit_gen(e, 400 * H, H) for e in short]
+        for rid in [lid] + sids:
+            assert srv.wait(rid, 120.0) == fb.REQ_DONE
+        lres = srv.result(lid)
+        sres = [srv.result(r) for r in sids]
+    assert max(r["t_done"] for r in sres) < lres["t_done"]
+    assert np.all(lres["steps"] == serve.request_steps(5000 * H, H))
 
 
 def test_cancel_and_errors(fb):
