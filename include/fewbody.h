@@ -242,11 +242,14 @@ fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
  * advances the scheduled requests' systems by up to steps_per_quantum steps
  * in one fused launch: every resident request (FB_POLICY_FAIR), or those
  * with at least long_steps steps left plus, least remaining work first,
- * others until about quantum_tiles tiles are scheduled (FB_POLICY_SRPT).  Finished requests are copied back and their
- * memory is reused.  For a fixed plan table a request's results do not
- * depend on what else is resident or on the schedule.  (No counterpart in
- * the paper, whose host only sets up, loads, calls and examines -- Section
- * 5.3; this is the serving form of its many steps per kernel call.) */
+ * others until they fill about quantum_tiles tiles (FB_POLICY_SRPT).
+ * Finished requests are copied back and their memory is reused.  The kernel
+ * mappings (the plan table's fused-kernel class in entry 0, auto meaning
+ * body-per-lane, and per-n mappings) are fixed when the server is created,
+ * so a request's results do not depend on what else is resident, on the
+ * schedule or on later fb_set_plan calls.  (No counterpart in the paper,
+ * whose host only sets up, loads, calls and examines -- Section 5.3; this is
+ * the serving form of its many steps per kernel call.) */
 typedef struct fb_server fb_server;
 
 enum { FB_REQ_QUEUED = 0, FB_REQ_RUNNING = 1, FB_REQ_DONE = 2, FB_REQ_CANCELLED = 3,
@@ -260,9 +263,9 @@ typedef struct {
     int32_t max_resident;       /* requests resident at once (0: 4096)              */
     int32_t steps_per_quantum;  /* steps per scheduled system per quantum (0: 2000) */
     int32_t policy;             /* FB_POLICY_FAIR / FB_POLICY_SRPT                  */
-    int32_t quantum_tiles;      /* SRPT: tiles per quantum to schedule, whole
-                                   requests in order of remaining work (0: twice
-                                   the waves the fused launch keeps resident)       */
+    int32_t quantum_tiles;      /* SRPT: tiles per quantum for the requests chosen
+                                   by remaining work, whole requests (0: twice the
+                                   waves the fused launch keeps resident)           */
     int32_t chunk_slots;        /* systems per pool chunk, multiple of 64 (0: 512)  */
     int32_t long_steps;         /* SRPT: requests with at least this many steps left
                                    run in every quantum, whatever their work, since

@@ -270,6 +270,11 @@ struct fb_server {
     fb_server_opts opts;
     int device = 0;
     int num_cu = 256;
+    // Kernel mapping, fixed at creation from the plan table (entry 0's class,
+    // auto meaning body-per-lane; per-n mappings), so a request's arithmetic
+    // never depends on what else is resident or on later plan changes.
+    int cls = 0, waves_per_group = 2, groups_per_cu = 8;
+    int mapping[kMaxBodies + 1] = {0};
     hipStream_t stream = nullptr;
     bool own_stream = false;
     char *d_arena = nullptr;
@@ -497,10 +502,10 @@ fb_status grow(T *&p, size_t &cap, size_t need)
 }
 
 // Fused-kernel mapping of body count n under class cls.
-int server_mapping(int cls, int n)
+int server_mapping(const fb_server *S, int n)
 {
-    const int lim = persistent_spl_limit(cls, 0);
-    return (n <= lim && (get_plan(n).mapping == MAP_SPL || cls == 1)) ? MAP_SPL : MAP_BPL;
+    const int lim = persistent_spl_limit(S->cls, 0);
+    return (n <= lim && (S->mapping[n] == MAP_SPL || S->cls == 1)) ? MAP_SPL : MAP_BPL;
 }
 
 // One quantum.  Returns the requests it finished (reached their step count
@@ -509,16 +514,7 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
 {
     const int Q = S->opts.steps_per_quantum;
     sys_steps = 0.0;
-    // The fused-kernel class is fixed by the plan (auto: body-per-lane), never
-    // by the resident mix, so every request sees the same arithmetic alone
-    // and among others.
-    const Plan p0 = get_plan(0);
-    const int cls = p0.mapping == MAP_SPL ? 1 : 0;
-    const int W = std::max(1, std::min(4, p0.waves_per_group));
-    int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
-    const int occ = persistent_max_groups_per_cu(0, cls, W);
-    if (occ > 0)
-        gpc = std::min(gpc, occ);
+    const int cls = S->cls, W = S->waves_per_group, gpc = S->groups_per_cu;
 
     std::vector<Request *> live;
     for (Request *R : S->resident) {
@@ -541,21 +537,21 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
             long long t = 0;
             for (int n = 2; n <= kMaxBodies; ++n)
                 if (R->cnt[n]) {
-                    const int cap = tile_systems(server_mapping(cls, n), n);
+                    const int cap = tile_systems(server_mapping(S, n), n);
                     t += (R->cnt[n] + cap - 1) / cap;
                 }
             return t;
         };
+        // Long requests run every quantum and do not count against the
+        // target: it bounds only the part chosen by remaining work.
         const long long L = S->opts.long_steps;
         long long tiles = 0;
         std::vector<Request *> rest;
         for (Request *R : live) {
-            if (L > 0 && R->total_steps - R->done_steps >= L) {
+            if (L > 0 && R->total_steps - R->done_steps >= L)
                 sched.push_back(R);
-                tiles += tiles_of(R);
-            } else {
+            else
                 rest.push_back(R);
-            }
         }
         for (Request *R : rest) {
             if (tiles >= target)
@@ -601,7 +597,7 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
     for (size_t i = 0; i < runs.size();) {
         Chunk *c = runs[i].c;
         const int n = c->n;
-        const int map = server_mapping(cls, n);
+        const int map = server_mapping(S, n);
         const int cap = tile_systems(map, n);
         const int bi = (int)S->h_buckets.size();
         S->h_buckets.push_back(c->B);
@@ -862,6 +858,15 @@ fb_status fb_server_create(const fb_server_opts *po, void *hip_stream, fb_server
     hipDeviceProp_t prop;
     FB_HIP(hipGetDeviceProperties(&prop, S->device));
     S->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const Plan p0 = get_plan(0);
+    S->cls = p0.mapping == MAP_SPL ? 1 : 0;
+    S->waves_per_group = std::max(1, std::min(4, p0.waves_per_group));
+    S->groups_per_cu = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
+    const int occ = persistent_max_groups_per_cu(0, S->cls, S->waves_per_group);
+    if (occ > 0)
+        S->groups_per_cu = std::min(S->groups_per_cu, occ);
+    for (int n = 2; n <= kMaxBodies; ++n)
+        S->mapping[n] = get_plan(n).mapping;
     if (hip_stream) {
         S->stream = (hipStream_t)hip_stream;
     } else {
