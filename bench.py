@@ -10,15 +10,20 @@ timed steps.
 
 Printed as one JSON line, with
   roofline      achieved algorithmic FP64 FLOP/s of the integration kernel
-                (HIP events on its launch stream) against the FP64 vector peak;
+                (HIP events on its launch stream) against the FP64 vector peak
+                and against this device's measured FP64 FMA ceiling; the
+                counter-derived FP64 FLOP/s and VALU occupancy where the
+                kernel's hardware counters are on record; HBM traffic;
   p50/p99       solve latency of the serving trace (Poisson arrivals at
                 200 req/s, 1..4096 systems of 3..10 bodies per request);
   cpu_baseline  the CPU oracle timed on this host's cores on a bounded sample;
-  extras        ragged 65536 x (3..15): autotuned plans, plain per-bucket
-                launches vs the fused persistent launch; uneven lifetimes
-                65536 x (4..8) with adaptive steps and stop rules on a bounded
-                horizon: plain launches vs persistent quanta with compaction;
-                the serving report.
+  extras        the serving report (with the single-tile latency floor);
+                with --extras also: ragged 65536 x (3..15), autotuned plans,
+                plain per-bucket launches vs the fused persistent launch;
+                uneven lifetimes 65536 x (4..8) with adaptive steps and stop
+                rules on a bounded horizon, plain launches vs persistent
+                quanta with compaction; Section 5.1's initial conditions at
+                Table 3's size, beside the paper's times.
 """
 from __future__ import annotations
 
@@ -39,7 +44,22 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 # FETCH_SIZE / WRITE_SIZE counter passes (scaled by a 256 MiB copy kernel's
 # reading) recorded in profiles/, keyed by the kernel source they measured.
 MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1}
+# Hardware counters of the same kernel on this workload (profiles/), keyed the
+# same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
+# lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
+# GRBM_GUI_ACTIVE per XCD x SIMDs); the shader clock those cycles imply.
+MEASURED_COUNTERS = {}
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
+# Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
+# initial conditions for one time unit with the Hermite integrator, on the
+# paper's four machines (context only: other hardware).
+PAPER_TABLE3_SECONDS = {
+    3: {"cluster1": 140.008, "cluster2": 35.951, "server1": 29.290, "workstation": 30.482},
+    4: {"cluster1": 203.036, "cluster2": 65.284, "server1": 52.635, "workstation": 53.132},
+    5: {"cluster1": 310.685, "cluster2": 100.800, "server1": 69.346, "workstation": 81.880},
+    6: {"cluster1": 807.346, "cluster2": 121.908, "server1": 102.880, "workstation": 103.536},
+    10: {"cluster1": 1874.480, "cluster2": 444.202, "server1": 577.674, "workstation": 362.020},
+}
 
 
 def kernel_source_hash() -> str:
@@ -145,8 +165,48 @@ def lifetimes_extras(fb, gen, torch, log, orbits=100.0, quantum=2000):
     return out
 
 
+def step_latency(fb, gen, n, mapping, h=2 * math.pi / 1000, steps=20000):
+    """Seconds per step of a single tile (64 systems system-per-lane, or
+    floor(64/n) body-per-lane) with the device otherwise idle: the floor of
+    any request's latency per step."""
+    k = 64 if mapping == fb.MAP_SPL else 64 // n
+    ens = gen.ragged_hill(k, seed=9, n_lo=n, n_hi=n)
+    saved = fb.get_plan(n)
+    fb.set_plan(n, mapping, 1, 0)
+    try:
+        E = fb.from_gen(ens)
+        E.integrate_steps(100, h)
+        E.synchronize()
+        t0 = time.perf_counter()
+        E.integrate_steps(steps, h)
+        E.synchronize()
+        dt = time.perf_counter() - t0
+        E.close()
+    finally:
+        fb.set_plan(n, *saved)
+    return dt / steps
+
+
+def paper_ic_extras(fb, gen, torch, log, n_sys=131072, h=1e-3, t_end=1.0):
+    """Section 5.1's initial conditions at Table 3's size and length (one
+    time unit at h = 1e-3), next to the paper's seconds on its machines."""
+    rows = []
+    steps = int(round(t_end / h))
+    for n in sorted(PAPER_TABLE3_SECONDS):
+        ens = gen.paper_ics(n_sys, n)
+        dt, st = timed(fb, torch, ens, lambda E: E.integrate_steps(steps, h))
+        assert (st["status"] == fb.DONE).all()
+        rows.append({"n": n, "seconds": dt, "system_steps_per_s": n_sys * steps / dt,
+                     "fp64_tflops_algorithmic": n_sys * steps * flops_per_system_step(n) / dt / 1e12,
+                     "paper_table3_seconds": PAPER_TABLE3_SECONDS[n]})
+        log(f"[bench] paper ICs n={n}: {dt:.4f} s")
+    return {"workload": f"paper ICs (Section 5.1): {n_sys} systems, equal planet masses 1e-3, circular, "
+                        f"coplanar, a_i = 1.4^(i-1); {steps} steps of h = {h:g} (one time unit); default plans",
+            "rows": rows}
+
+
 def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, policy="srpt",
-                   cls="bpl", quantum_tiles=0, long_steps=0):
+                   cls="spl", quantum_tiles=0, long_steps=300000):
     from paper_1208_1157_amd import serve
     trace = gen.serving_trace(n_req, rate=200.0, seed=4)
     saved = fb.get_plan(0)
@@ -165,6 +225,11 @@ def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, po
     rep["long_steps"] = long_steps
     rep["workload"] = (f"serving: {n_req} requests, Poisson 200 req/s, 1..4096 systems (log-uniform) of 3..10 "
                        f"bodies, t_end 2pi*10^U(1,3), dt 2pi/1000")
+    lat = {"n3_system_per_lane": step_latency(fb, gen, 3, fb.MAP_SPL),
+           "n10_system_per_lane": step_latency(fb, gen, 10, fb.MAP_SPL),
+           "n10_body_per_lane": step_latency(fb, gen, 10, fb.MAP_BPL)}
+    rep["single_tile_step_latency_s"] = lat
+    rep["min_latency_1e6_steps_s"] = {k: v * 1e6 for k, v in lat.items()}
     return rep
 
 
@@ -185,11 +250,11 @@ def main():
     ap.add_argument("--serve-quantum", type=int, default=2000)
     ap.add_argument("--serve-policy", choices=["fair", "srpt"], default="srpt",
                     help="server scheduling: every resident request per quantum, or least remaining work first")
-    ap.add_argument("--serve-class", choices=["bpl", "spl"], default="bpl",
+    ap.add_argument("--serve-class", choices=["bpl", "spl"], default="spl",
                     help="fused-kernel class the server runs")
     ap.add_argument("--serve-quantum-tiles", type=int, default=0,
                     help="SRPT tiles per quantum (0: the server's default)")
-    ap.add_argument("--serve-long-steps", type=int, default=0,
+    ap.add_argument("--serve-long-steps", type=int, default=300000,
                     help="SRPT: requests with at least this many steps left run every quantum")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 256 MiB device copy (HBM counter calibration)")
@@ -220,6 +285,15 @@ def main():
     v_d = torch.from_numpy(ens.vel).to(dev)
     torch.cuda.synchronize()
 
+    default_plans = {n: fb.get_plan(n) for n in [0] + list(range(2, 17))}
+
+    def restore_plans():
+        for n, pl in default_plans.items():
+            fb.set_plan(n, *pl)
+
+    # the headline launch: system per lane, four waves per workgroup
+    fb.set_plan(3, fb.MAP_SPL, 4, 0)
+
     def one_step():
         E = fb.Ensemble(ens.n_body, m_d, x_d, v_d)
         E.integrate_steps(K, h)
@@ -249,6 +323,10 @@ def main():
     flops_per_launch = ens.n_sys * K * flops_per_system_step(3)
     achieved = flops_per_launch / kern_avg_s / 1e12
     m, w, _ = fb.get_plan(3)
+    probe = fb.fp64_fma_ceiling()
+    counters = MEASURED_COUNTERS.get(kernel_source_hash())
+    counter_tflops = (counters["fp64_flops_per_system_step"] * ens.n_sys * K / kern_avg_s / 1e12
+                      if counters else None)
     result = {
         "metric": METRIC,
         "value": value,
@@ -272,12 +350,16 @@ def main():
                      "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
                      "kernel": "k_plain_spl<3>", "kernel_avg_ms": kern_avg_s * 1e3,
                      "kernel_launches": launches,
-                     "flops_per_launch": flops_per_launch},
+                     "flops_per_launch": flops_per_launch,
+                     "fma_probe_tflops": probe, "frac_of_fma_probe": achieved / probe if probe else None,
+                     "counter_tflops": counter_tflops, "counters": counters},
+        "pair_interactions_per_s": value * 2 * 3,
     }
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
     extras = {}
+    restore_plans()
     if not args.no_serve:
         rep = serving_report(fb, gen, log, args.serve_requests, args.serve_max_resident, args.serve_quantum,
                              args.serve_policy, args.serve_class, args.serve_quantum_tiles,
@@ -287,7 +369,10 @@ def main():
         extras["serving"] = rep
     if args.extras:
         extras["ragged"] = ragged_extras(fb, gen, torch, log)
+        restore_plans()
         extras["lifetimes"] = lifetimes_extras(fb, gen, torch, log)
+        restore_plans()
+        extras["paper_ics"] = paper_ic_extras(fb, gen, torch, log)
     if extras:
         result["extras"] = extras
     if not args.no_cpu:

@@ -72,7 +72,7 @@ enum { FB_STOP_ENCOUNTER = 1, FB_STOP_EJECT = 2 };
 
 /* Lane mappings of a launch plan. */
 enum {
-    FB_MAP_AUTO = 0,             /* use the plan table                         */
+    FB_MAP_AUTO = 0,             /* chosen per bucket at launch (see plans)    */
     FB_MAP_SYSTEM_PER_LANE = 1,  /* one system per lane, all state in VGPRs    */
     FB_MAP_BODY_PER_LANE = 2     /* one body per lane, partners through LDS    */
 };
@@ -188,13 +188,16 @@ fb_status fb_ensemble_destroy(fb_ensemble *e);
 
 /* ---------------------------------------------------------------- plans */
 /* The launch plan of body count n: lane mapping (FB_MAP_*) and waves per
- * workgroup (1..4).  Entry n = 0 is the fused persistent launch: its mapping
- * selects the kernel class (FB_MAP_SYSTEM_PER_LANE: full register file,
- * system-per-lane tiles up to n = 10, n = 5 with adaptive steps or stop
- * rules; FB_MAP_BODY_PER_LANE: <= 128 VGPRs, system-per-lane tiles only for
- * n <= 3; FB_MAP_AUTO: the former when every bucket fits it), plus waves per
- * workgroup and workgroups per CU (1..32, 0 = default).  Plans are
- * process-wide; the autotuner sets them. */
+ * workgroup (1..4) of its plain launches.  System-per-lane is built for
+ * n <= 10 (n <= 5 with adaptive steps or stop rules); FB_MAP_AUTO (the
+ * default) picks it for a bucket whose 64-system tiles give every SIMD of
+ * the device a wavefront, and body-per-lane otherwise.  Entry n = 0 is the
+ * fused persistent launch: its mapping selects the kernel class
+ * (FB_MAP_SYSTEM_PER_LANE: full register file, system-per-lane tiles where n
+ * allows; FB_MAP_BODY_PER_LANE: <= 128 VGPRs, body-per-lane tiles only;
+ * FB_MAP_AUTO: the former when every bucket allows it and its tiles give
+ * every SIMD a wavefront), plus waves per workgroup and workgroups per CU
+ * (1..32, 0 = default).  Plans are process-wide; the autotuner sets them. */
 fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group,
                       int32_t groups_per_cu);
 fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,
@@ -230,6 +233,14 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
  * the last reset. */
 fb_status fb_profile_enable(int32_t on);
 fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
+
+/* The device's achievable FP64 vector rate, for the roofline beside the
+ * published peak: the best of two timed launches of independent FP64 FMA
+ * chains (8 workgroups of 256 lanes per CU, 16 chains per lane), counted at
+ * 2 flop per FMA, in TFLOP/s.  Allocates and frees its own buffers on the
+ * current device and synchronises.  (A measurement utility; it computes
+ * nothing of the method.) */
+fb_status fb_fp64_fma_ceiling(double *tflops);
 
 /* ---------------------------------------------------------------- serving */
 /* A continuous-batching integration server.  Requests (an ensemble with its

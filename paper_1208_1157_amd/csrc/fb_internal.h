@@ -106,6 +106,9 @@ hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos
 hipError_t launch_diag(const Bucket &B, double *energy, double *angmom,
                        hipStream_t s);
 hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s);
+// FP64 FMA issue-ceiling probe: blocks x 256 lanes, iters x kFmaChains FMAs
+// per lane (kFmaChains = 16); out holds blocks x 256 doubles.
+hipError_t launch_fma_probe(double *out, int blocks, int iters, hipStream_t s);
 size_t persistent_lds_bytes(int spl_class, int waves_per_group);
 int persistent_max_groups_per_cu(int adv, int spl_class, int waves_per_group);
 // Largest n a persistent tile runs system-per-lane for, by kernel class.

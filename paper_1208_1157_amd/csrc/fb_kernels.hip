@@ -1275,6 +1275,29 @@ __global__ void k_count_active(Bucket B, int *count)
         atomicAdd(count, __popcll(mask));
 }
 
+// FP64 issue-ceiling probe for the roofline: each lane runs kFmaChains
+// independent FMA chains (a <- a*b + c, b slightly below 1 so values stay
+// bounded), so the rate is set by VALU issue rather than FMA latency.
+constexpr int kFmaChains = 16;
+
+__global__ __launch_bounds__(256) void k_fma_probe(double *out, int iters, double b, double c)
+{
+    double acc[kFmaChains];
+#pragma unroll
+    for (int k = 0; k < kFmaChains; ++k)
+        acc[k] = 1e-3 * threadIdx.x + k;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kFmaChains; ++k)
+            acc[k] = fma(acc[k], b, c);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kFmaChains; ++k)
+        sum += acc[k];
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
+}
+
 inline dim3 grid_for(int n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
 
 }  // namespace
@@ -1475,6 +1498,12 @@ hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s)
     if (B.count == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_count_active, grid_for(B.count, 256), dim3(256), 0, s, B, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fma_probe(double *out, int blocks, int iters, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fma_probe, dim3(blocks), dim3(256), 0, s, out, iters, 0.999999, 1e-6);
     return hipGetLastError();
 }
 

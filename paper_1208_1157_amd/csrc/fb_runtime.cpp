@@ -67,8 +67,10 @@ void init_plans_locked()
 {
     if (g_plan_init)
         return;
+    // Mapping chosen per bucket at launch (auto); four waves per group for
+    // the register-light small systems, two otherwise.
     for (int n = 0; n <= kMaxBodies; ++n)
-        g_plan[n] = Plan{n <= 3 ? MAP_SPL : MAP_BPL, n <= 3 ? 4 : 2, 0};
+        g_plan[n] = Plan{0, n <= 3 ? 4 : 2, 0};
     g_plan[0] = Plan{0, 2, 8};   // fused-kernel class chosen per launch
     g_plan_init = true;
 }
@@ -409,8 +411,9 @@ fb_status run_plain(fb_ensemble *e, const fb_opts &o, long long step_bound)
         for (const Bucket &B : e->buckets) {
             const Plan p = get_plan(B.n);
             const StepParams P = make_params(o, quantum);
+            const int map = plain_mapping(p, B, P.adaptive || P.stop_rules, e->num_cu);
             ProfScope ps(e->stream);
-            FB_HIP(launch_plain(B, p.mapping, p.waves_per_group, P, e->stream));
+            FB_HIP(launch_plain(B, map, p.waves_per_group, P, e->stream));
         }
         if (quantum == INT_MAX)
             return FB_OK;
@@ -862,10 +865,8 @@ fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group, int32
     std::lock_guard<std::mutex> lk(g_plan_mu);
     init_plans_locked();
     Plan &p = g_plan[n];
-    if (mapping != FB_MAP_AUTO)
-        p.mapping = mapping == FB_MAP_SYSTEM_PER_LANE ? MAP_SPL : MAP_BPL;
-    else if (n == 0)
-        p.mapping = 0;
+    p.mapping = mapping == FB_MAP_AUTO ? 0
+                : mapping == FB_MAP_SYSTEM_PER_LANE ? MAP_SPL : MAP_BPL;
     p.waves_per_group = waves_per_group;
     p.groups_per_cu = groups_per_cu;
     return FB_OK;
@@ -1064,6 +1065,58 @@ fb_status fb_profile_read(double *kernel_ms, int64_t *launches)
 }
 
 const char *fb_last_error(void) { return g_err.c_str(); }
+
+fb_status fb_fp64_fma_ceiling(double *tflops)
+{
+    if (!tflops)
+        return fail(FB_E_INVAL, "tflops is NULL");
+    *tflops = 0.0;
+    int dev = 0;
+    FB_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    FB_HIP(hipGetDeviceProperties(&prop, dev));
+    const int cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const int blocks = 8 * cu, iters = 20000;
+    double *out = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    fb_status st = FB_OK;
+    hipError_t e = hipMalloc((void **)&out, sizeof(double) * 256 * (size_t)blocks);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    float best_ms = 0.0f;
+    for (int rep = 0; e == hipSuccess && rep < 3; ++rep) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess)
+            e = launch_fma_probe(out, blocks, iters, s);
+        if (e == hipSuccess)
+            e = hipEventRecord(b, s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && rep > 0 && (best_ms == 0.0f || ms < best_ms))
+            best_ms = ms;
+    }
+    if (e != hipSuccess)
+        st = hip_fail(e, "FP64 FMA probe");
+    else if (best_ms > 0.0f)
+        *tflops = 2.0 * 16.0 * iters * 256.0 * blocks / (best_ms * 1e-3) / 1e12;
+    if (a)
+        (void)hipEventDestroy(a);
+    if (b)
+        (void)hipEventDestroy(b);
+    if (s)
+        (void)hipStreamDestroy(s);
+    if (out)
+        (void)hipFree(out);
+    return st;
+}
 
 const char *fb_version(void) { return "fewbody-hip 0.1 (gfx950, FP64 Hermite P(EC)^2)"; }
 

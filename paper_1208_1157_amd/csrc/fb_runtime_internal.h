@@ -32,6 +32,20 @@ struct Plan {
 };
 Plan get_plan(int n);
 
+// Lane mapping of a plain launch over bucket B: the plan's, or (auto)
+// system-per-lane when n allows it and the bucket's 64-system tiles give
+// every SIMD of the device a wavefront, else body-per-lane, whose n lanes
+// per system spread a small bucket over more of the device.
+inline int plain_mapping(const Plan &p, const Bucket &B, bool adv, int num_cu)
+{
+    const int lim = adv ? kMaxSplAdv : kMaxSplBodies;
+    if (p.mapping == MAP_BPL || B.n > lim)
+        return MAP_BPL;
+    if (p.mapping == MAP_SPL)
+        return MAP_SPL;
+    return (B.count + 63) / 64 >= 4LL * num_cu ? MAP_SPL : MAP_BPL;
+}
+
 // Fused persistent kernel class for a launch over buckets of these body
 // counts: the plan's choice, or (auto) the system-per-lane class when every
 // bucket can run system-per-lane in it and its tiles (64 systems each) give

@@ -92,6 +92,7 @@ _SIGS = {
     "fb_server_opts_default": (None, [ctypes.POINTER(FbServerOpts)]),
     "fb_server_create": (ctypes.c_int, [ctypes.POINTER(FbServerOpts), _p, ctypes.POINTER(_p)]),
     "fb_server_request_bytes": (_sz, [ctypes.POINTER(FbServerOpts), _i32, _p]),
+    "fb_fp64_fma_ceiling": (ctypes.c_int, [_p]),
     "fb_server_submit": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p, _d, _d, ctypes.POINTER(_i64)]),
     "fb_server_poll": (ctypes.c_int, [_p, _i64, ctypes.POINTER(_i32)]),
     "fb_server_wait": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(_i32)]),
@@ -166,6 +167,13 @@ def get_plan(n):
 
 def profile_enable(on=True):
     _check(_lib.fb_profile_enable(1 if on else 0))
+
+
+def fp64_fma_ceiling() -> float:
+    """Achievable FP64 FMA rate of the current device in TFLOP/s (fb_fp64_fma_ceiling)."""
+    v = ctypes.c_double()
+    _check(_lib.fb_fp64_fma_ceiling(ctypes.byref(v)))
+    return v.value
 
 
 def profile_read():

@@ -92,6 +92,8 @@ def test_plan_table(fbmod):
     m0 = fbmod.get_plan(5)
     fbmod.set_plan(5, fbmod.MAP_SPL, 2, 0)
     assert fbmod.get_plan(5) == (fbmod.MAP_SPL, 2, 0)
+    fbmod.set_plan(5, fbmod.MAP_AUTO, 2, 0)
+    assert fbmod.get_plan(5) == (fbmod.MAP_AUTO, 2, 0)     # auto is a setting, not "keep"
     fbmod.set_plan(5, m0[0], m0[1], m0[2])
     with pytest.raises(fbmod.FewbodyError):
         fbmod.set_plan(12, fbmod.MAP_SPL, 1, 0)     # SPL built for n <= 10 only
@@ -129,3 +131,7 @@ def test_server_request_bytes(fbmod):
     assert fbmod.server_request_bytes([5], policy=7) == 0
     assert fbmod.server_request_bytes([5], long_steps=-1) == 0
     assert fbmod.server_request_bytes([]) > 0
+
+
+def test_fma_ceiling_rejects_null(fbmod):
+    assert fbmod.lib().fb_fp64_fma_ceiling(None) == fbmod.E_INVAL

@@ -338,3 +338,30 @@ def test_paper_step_rule_parity(plans, ora, mapping):
         ev = per_system_rel_err([ens.n_body[s]], st["vel"][sl], o["vel"])[0]
         assert ex <= REL_TOL and ev <= REL_TOL, (s, ex, ev)
         assert st["t"][s] == t_end
+
+
+def test_auto_mapping_matches_the_explicit_launch(plans):
+    """FB_MAP_AUTO resolves per bucket: system-per-lane for a bucket that
+    gives every SIMD a wavefront, body-per-lane for a small one; results are
+    bit-identical to the explicitly planned launch (and differ from the other
+    mapping wherever the two mappings round differently)."""
+    fb = plans
+    big = gen.ragged_hill(65536, seed=5, n_lo=6, n_hi=6)
+    small = gen.ragged_hill(700, seed=6, n_lo=6, n_hi=6)
+    for ens, expect, other in ((big, fb.MAP_SPL, fb.MAP_BPL), (small, fb.MAP_BPL, fb.MAP_SPL)):
+        say("auto mapping", ens.n_sys)
+        fb.set_plan(6, fb.MAP_AUTO, 2, 0)
+        a, _, _ = run_gpu(fb, ens, 40, H2000)
+        fb.set_plan(6, expect, 2, 0)
+        b, _, _ = run_gpu(fb, ens, 40, H2000)
+        fb.set_plan(6, other, 2, 0)
+        c, _, _ = run_gpu(fb, ens, 40, H2000)
+        assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+        if not np.array_equal(b["pos"], c["pos"]):
+            assert not np.array_equal(a["pos"], c["pos"])
+
+
+def test_fp64_fma_ceiling(fb):
+    v = fb.fp64_fma_ceiling()
+    say("fma ceiling", v)
+    assert 5.0 < v < 100.0
