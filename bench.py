@@ -43,12 +43,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 # HBM bytes per launch of the integration kernel on this workload, from the
 # FETCH_SIZE / WRITE_SIZE counter passes (scaled by a 256 MiB copy kernel's
 # reading) recorded in profiles/, keyed by the kernel source they measured.
-MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1}
+MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1,
+                    "1c9dff3d544099cf": 92417308.4}
 # Hardware counters of the same kernel on this workload (profiles/), keyed the
 # same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
 # lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
 # GRBM_GUI_ACTIVE per XCD x SIMDs); the shader clock those cycles imply.
-MEASURED_COUNTERS = {}
+MEASURED_COUNTERS = {
+    "1c9dff3d544099cf": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9671,
+                         "shader_clock_ghz": 2.018, "valu_insts_per_system_step": 388.01},
+}
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
 # initial conditions for one time unit with the Hermite integrator, on the
