@@ -87,15 +87,15 @@ def host_threads() -> int:
     return max(1, min(16, c))
 
 
-def cpu_baseline(ens, h, target_s=12.0):
+def cpu_baseline(ens, h, target_s=15.0):
     """The oracle (plain FP64 C, one system per thread) on this host's cores,
     on all systems of the ensemble for a bounded number of steps."""
     import oracle
     nt = host_threads()
-    cal = ens.subset(range(min(ens.n_sys, 2048)))
+    cal = ens.subset(range(min(ens.n_sys, 16384)))
     t0 = time.perf_counter()
-    oracle.ensemble_fixed(cal.n_body, cal.mass, cal.pos, cal.vel, h, 50, nthreads=nt)
-    rate = cal.n_sys * 50 / (time.perf_counter() - t0)
+    oracle.ensemble_fixed(cal.n_body, cal.mass, cal.pos, cal.vel, h, 40, nthreads=nt)
+    rate = cal.n_sys * 40 / (time.perf_counter() - t0)
     steps = max(10, int(rate * target_s / ens.n_sys))
     t0 = time.perf_counter()
     oracle.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, h, steps, nthreads=nt)
@@ -103,7 +103,7 @@ def cpu_baseline(ens, h, target_s=12.0):
     return {"value": ens.n_sys * steps / dt, "unit": "system-steps/s", "cores": nt,
             "kind": "oracle",
             "sample": f"all {ens.n_sys} systems x {steps} steps (of the workload's steps), "
-                      f"{dt:.1f} s, std::thread-free pthreads static partition"}
+                      f"{dt:.1f} s, pthreads with a static partition by system"}
 
 
 def timed(fb, torch, ens, fn):
