@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the ragged (autotuned, plain vs persistent) and uneven-lifetimes "
                          "(plain vs compaction) comparisons")
+    ap.add_argument("--lifetimes-orbits", type=float, default=100.0,
+                    help="horizon of the uneven-lifetimes extra in inner orbits (the workload's is 1e4)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-max-resident", type=int, default=4096)
@@ -374,7 +376,7 @@ def main():
     if args.extras:
         extras["ragged"] = ragged_extras(fb, gen, torch, log)
         restore_plans()
-        extras["lifetimes"] = lifetimes_extras(fb, gen, torch, log)
+        extras["lifetimes"] = lifetimes_extras(fb, gen, torch, log, orbits=args.lifetimes_orbits)
         restore_plans()
         extras["paper_ics"] = paper_ic_extras(fb, gen, torch, log)
     if extras:
