@@ -1,7 +1,7 @@
-"""CPU oracle for the fewbody Hermite integrator -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for the fewbody integrators -- TEST INFRASTRUCTURE ONLY.
 
-A ctypes wrapper around ``hermite_oracle.c`` (plain FP64 C, built with
-``-O2 -ffp-contract=off``).  Only the test suite, the smoke check and the
+A ctypes wrapper around ``hermite_oracle.c`` and ``mvs_oracle.c`` (plain FP64
+C, built with ``-O2 -ffp-contract=off``).  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package; the product library
 never does.  It shares no code with the HIP path: the only inputs both sides
 see come from the seeded generators.
@@ -18,19 +18,20 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "hermite_oracle.c")
+SRCS = [os.path.join(HERE, "hermite_oracle.c"), os.path.join(HERE, "mvs_oracle.c")]
 LIB = os.environ.get("FEWBODY_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
-ACTIVE, DONE, ENCOUNTER, EJECTED, NONFINITE, STALLED_DT, MAXSTEPS = range(7)
+ACTIVE, DONE, ENCOUNTER, EJECTED, NONFINITE, STALLED_DT, MAXSTEPS, UNBOUND = range(8)
 STOP_ENCOUNTER, STOP_EJECT = 1, 2
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain FP64, no contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    stale = not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(s) for s in SRCS)
+    if force or stale:
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-                               "-Wall", "-fPIC", "-shared", "-o", tmp, SRC, "-lm", "-lpthread"])
+                               "-Wall", "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm", "-lpthread"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -63,6 +64,15 @@ def lib():
         L.ora_ensemble_fixed.restype = i
         L.ora_ensemble_energy.argtypes = [i, p, p, p, p, p, p]
         L.ora_ensemble_energy.restype = i
+        L.ora_mvs_to_helio.argtypes = [i, p, p, p, p, p, p, p]
+        L.ora_mvs_from_helio.argtypes = [i, p, p, p, p, p, p, p]
+        L.ora_kepler_drift.argtypes = [d, p, p, d]
+        L.ora_kepler_drift.restype = i
+        L.ora_mvs_kick_acc.argtypes = [i, p, p, p]
+        L.ora_mvs_step.argtypes = [i, p, p, p, p, p, d]
+        L.ora_mvs_step.restype = i
+        L.ora_integrate_mvs.argtypes = [i, p, p, p, d, l, p]
+        L.ora_integrate_mvs.restype = i
         _lib = L
     return _lib
 
@@ -206,3 +216,60 @@ def ensemble_energy(n_body, mass, pos, vel):
     if rc != 0:
         raise ValueError("oracle rejected arguments")
     return E, L
+
+
+# ---------------------------------------------------------------- MVS
+def mvs_to_helio(mass, pos, vel):
+    """(Q, V, X, Vc): heliocentric planet positions and barycentric velocities
+    (row 0 zero), centre of mass and its velocity (mvs_oracle.c)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)), _f64(vel, (n, 3))
+    Q, V, X, Vc = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(3), np.zeros(3)
+    lib().ora_mvs_to_helio(n, _p(m), _p(x), _p(v), _p(Q), _p(V), _p(X), _p(Vc))
+    return Q, V, X, Vc
+
+
+def mvs_from_helio(mass, Q, V, X, Vc):
+    m = _f64(mass)
+    n = m.shape[0]
+    Q, V, X, Vc = _f64(Q, (n, 3)), _f64(V, (n, 3)), _f64(X), _f64(Vc)
+    x, v = np.zeros((n, 3)), np.zeros((n, 3))
+    lib().ora_mvs_from_helio(n, _p(m), _p(Q), _p(V), _p(X), _p(Vc), _p(x), _p(v))
+    return x, v
+
+
+def kepler_drift(mu, r, v, dt):
+    """(r, v) after dt on the Kepler orbit about mu, or None if unbound."""
+    r, v = _f64(r).copy(), _f64(v).copy()
+    rc = lib().ora_kepler_drift(float(mu), _p(r), _p(v), float(dt))
+    return None if rc != 0 else (r, v)
+
+
+def mvs_kick_acc(mass, Q):
+    m = _f64(mass)
+    n = m.shape[0]
+    Q = _f64(Q, (n, 3))
+    acc = np.zeros((n, 3))
+    lib().ora_mvs_kick_acc(n, _p(m), _p(Q), _p(acc))
+    return acc
+
+
+def mvs_step(mass, Q, V, X, Vc, dt):
+    """One MVS step in place on copies; returns (status, Q, V, X)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    Q, V, X = _f64(Q, (n, 3)).copy(), _f64(V, (n, 3)).copy(), _f64(X).copy()
+    Vc = _f64(Vc)
+    st = lib().ora_mvs_step(n, _p(m), _p(Q), _p(V), _p(X), _p(Vc), float(dt))
+    return st, Q, V, X
+
+
+def integrate_mvs(mass, pos, vel, dt, nsteps):
+    """nsteps MVS steps of dt on inertial pos/vel; returns dict(pos, vel, status, steps)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)).copy(), _f64(vel, (n, 3)).copy()
+    done = ctypes.c_long()
+    st = lib().ora_integrate_mvs(n, _p(m), _p(x), _p(v), float(dt), int(nsteps), ctypes.byref(done))
+    return {"pos": x, "vel": v, "status": st, "steps": done.value}

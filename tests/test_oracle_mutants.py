@@ -2,8 +2,11 @@
 
 Each mutant is a plausible slip (a misread coefficient, a dropped power of
 h, a wrong sign, a swapped mass index, a double-counted pair, the star added
-first).  The copy is compiled into a temporary library and the pin suite is
-run against it in a subprocess; every mutant must make at least one pin fail.
+first; for MVS a wrong Kepler mu, a dropped or reversed reflex drift, a
+whole kick, the star in the kick, a wrong f function, a wrong mass).  The
+copy is compiled into a temporary library and the pin suite of the mutated
+source is run against it in a subprocess; every mutant must make at least
+one pin fail, and the unmutated copy must pass.
 """
 import os
 import subprocess
@@ -12,43 +15,82 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "oracle", "hermite_oracle.c")
+SOURCES = {"hermite": os.path.join(ROOT, "oracle", "hermite_oracle.c"),
+           "mvs": os.path.join(ROOT, "oracle", "mvs_oracle.c")}
+PINS = {"hermite": "test_oracle_pins.py", "mvs": "test_oracle_mvs.py"}
 
+# name -> (source, text, replacement)
 MUTANTS = {
-    "corrector_3_10": ("(3.0 / 20.0)", "(3.0 / 10.0)"),
-    "corrector_jerk_power": ("(7.0 * j0[k] + 2.0 * jk[k]) * h3 / 60.0",
+    "corrector_3_10": ("hermite", "(3.0 / 20.0)", "(3.0 / 10.0)"),
+    "corrector_jerk_power": ("hermite", "(7.0 * j0[k] + 2.0 * jk[k]) * h3 / 60.0",
                              "(7.0 * j0[k] + 2.0 * jk[k]) * h2 / 60.0"),
-    "corrector_v_sign": ("vc[k] = vp[k] - 0.5 * (a0[k] - ak[k]) * h",
+    "corrector_v_sign": ("hermite", "vc[k] = vp[k] - 0.5 * (a0[k] - ak[k]) * h",
                          "vc[k] = vp[k] - 0.5 * (a0[k] + ak[k]) * h"),
-    "predictor_v_power": ("0.5 * j0[k] * h2;", "0.5 * j0[k] * h;"),
-    "jerk_sign": ("J[c] = u[c] * s3 - 3.0 * ru * s2 * A[c];",
+    "predictor_v_power": ("hermite", "0.5 * j0[k] * h2;", "0.5 * j0[k] * h;"),
+    "jerk_sign": ("hermite", "J[c] = u[c] * s3 - 3.0 * ru * s2 * A[c];",
                   "J[c] = u[c] * s3 + 3.0 * ru * s2 * A[c];"),
-    "reaction_mass_index": ("a[3 * j + c] = a[3 * j + c] - m[i] * A[c];",
+    "reaction_mass_index": ("hermite", "a[3 * j + c] = a[3 * j + c] - m[i] * A[c];",
                             "a[3 * j + c] = a[3 * j + c] - m[j] * A[c];"),
-    "potential_double_count": ("pot = pot + m[i] * m[j]", "pot = pot + 2.0 * m[i] * m[j]"),
-    "star_first": ("    for (int i = 1; i < n; ++i)\n        for (int j = i + 1; j < n; ++j)\n"
+    "potential_double_count": ("hermite", "pot = pot + m[i] * m[j]", "pot = pot + 2.0 * m[i] * m[j]"),
+    "star_first": ("hermite",
+                   "    for (int i = 1; i < n; ++i)\n        for (int j = i + 1; j < n; ++j)\n"
                    "            pair_accumulate(i, j, m, x, v, a, jk);\n"
                    "    for (int j = 1; j < n; ++j)\n        pair_accumulate(0, j, m, x, v, a, jk);\n",
                    "    for (int j = 1; j < n; ++j)\n        pair_accumulate(0, j, m, x, v, a, jk);\n"
                    "    for (int i = 1; i < n; ++i)\n        for (int j = i + 1; j < n; ++j)\n"
                    "            pair_accumulate(i, j, m, x, v, a, jk);\n"),
-    "timestep_radial_factor": ("J[c] = mu * (u[c] / (r2 * rn) - 3.0 * ru * r[c] / (r2 * r2 * rn));",
+    "timestep_radial_factor": ("hermite",
+                               "J[c] = mu * (u[c] / (r2 * rn) - 3.0 * ru * r[c] / (r2 * r2 * rn));",
                                "J[c] = mu * (u[c] / (r2 * rn) - 2.0 * ru * r[c] / (r2 * r2 * rn));"),
+    # MVS: the two-body mu of Jacobi-style splittings, a dropped or reversed
+    # reflex drift, a whole kick where half belongs, the star in the kick, a
+    # wrong f function and the wrong mass in the star's velocity.
+    "mvs_kepler_mu": ("mvs", "ora_kepler_drift(m[0], Q + 3 * i, V + 3 * i, dt)",
+                      "ora_kepler_drift(m[0] + m[i], Q + 3 * i, V + 3 * i, dt)"),
+    "mvs_no_reflex_drift": ("mvs", "Q[3 * i + c] += h * P[c] / m[0];", "Q[3 * i + c] += 0.0 * P[c] / m[0];"),
+    "mvs_reflex_sign": ("mvs", "Q[3 * i + c] += h * P[c] / m[0];", "Q[3 * i + c] -= h * P[c] / m[0];"),
+    "mvs_whole_first_kick": ("mvs", "kick(n, m, Q, V, 0.5 * dt);\n    for (int i = 1;",
+                             "kick(n, m, Q, V, dt);\n    for (int i = 1;"),
+    "mvs_kick_includes_star": ("mvs", "for (int j = 1; j < n; ++j) {\n            if (j == i)",
+                               "for (int j = 0; j < n; ++j) {\n            if (j == i)"),
+    "mvs_f_function": ("mvs", "const double f = 1.0 - (a / r0) * (1.0 - c);",
+                       "const double f = 1.0 - (a / r0) * (1.0 + c);"),
+    "mvs_star_velocity_mass": ("mvs", "v[c] = Vc[c] - sp / m[0];", "v[c] = Vc[c] - sp / M;"),
 }
+
+
+def build_and_run_pins(tmp_path, which, old=None, new=None):
+    """Compile the oracle with `which`'s source mutated (old -> new; no
+    mutation when old is None) and the other source unchanged; run that
+    source's pin suite against it.  Returns the pytest process."""
+    srcs = []
+    for key, path in SOURCES.items():
+        text = open(path).read()
+        if key == which and old is not None:
+            assert text.count(old) == 1, "mutation site not found: the oracle changed"
+            text = text.replace(old, new)
+        out = tmp_path / os.path.basename(path)
+        out.write_text(text)
+        srcs.append(str(out))
+    so = tmp_path / "mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", str(so),
+                           *srcs, "-lm", "-lpthread"])
+    env = dict(os.environ, FEWBODY_ORACLE_LIB=str(so))
+    return subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", PINS[which])],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+
+
+@pytest.mark.parametrize("which", sorted(SOURCES))
+def test_unmutated_copy_passes(which, tmp_path):
+    """Control: the same build route without a mutation passes the pins, so
+    a mutant's failure is the mutation's doing."""
+    r = build_and_run_pins(tmp_path, which)
+    assert r.returncode == 0, r.stdout[-2000:]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, tmp_path):
-    old, new = MUTANTS[name]
-    src = open(SRC).read()
-    assert src.count(old) == 1, "mutation site not found: the oracle changed"
-    mut = tmp_path / "mutant.c"
-    mut.write_text(src.replace(old, new))
-    so = tmp_path / "mutant.so"
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", str(so),
-                           str(mut), "-lm", "-lpthread"])
-    env = dict(os.environ, FEWBODY_ORACLE_LIB=str(so))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    which, old, new = MUTANTS[name]
+    r = build_and_run_pins(tmp_path, which, old, new)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
