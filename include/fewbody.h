@@ -64,7 +64,9 @@ enum {
     FB_SYS_EJECTED = 3,    /* a planet farther than r_eject from its star     */
     FB_SYS_NONFINITE = 4,  /* a position or velocity became NaN or infinite   */
     FB_SYS_STALLED_DT = 5, /* adaptive step fell below 1e-12 * |t_end|        */
-    FB_SYS_MAXSTEPS = 6    /* hit fb_opts.max_steps                           */
+    FB_SYS_MAXSTEPS = 6,   /* hit fb_opts.max_steps                           */
+    FB_SYS_UNBOUND = 7     /* MVS: a planet's orbit about the star is not bound
+                              (state of the last completed step)              */
 };
 
 /* Stop-rule bits for fb_opts.stop_rules. */
@@ -151,6 +153,26 @@ fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body,
  * must be 0); NULL = defaults. */
 fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
                              const fb_opts *o);
+
+/* Mixed-variable symplectic integration (Section 2.2.2) of every active
+ * system by exactly n_steps fixed steps of dt, for systems of at most 8
+ * bodies (body 0 the central star).  Each step is the paper's sequence of
+ * sub-steps: Cartesian drift dt/2, kick dt/2, Keplerian drift dt, kick dt/2,
+ * Cartesian drift dt/2, in the democratic heliocentric splitting (Duncan,
+ * Levison & Lee 1998): planets follow Kepler orbits about the star (mu =
+ * m0) in heliocentric positions and barycentric velocities, kicks apply the
+ * planet-planet forces, and the drift is the star's reflex motion.  Kepler's
+ * equation is solved by Newton iteration per planet and step.  While the
+ * ensemble holds MVS state its rows keep the MVS variables (and the last
+ * kick's accelerations), so quanta and calls chain without conversion;
+ * fb_get_state and fb_diagnostics convert on the way out,
+ * fb_get_hermite_state fails with FB_E_STATE, and the next Hermite
+ * integration converts back and re-evaluates (a0, j0).  o: the quantum (o->
+ * steps_per_quantum); adaptive, stop_rules and compact must be 0 and the
+ * schedule plain.  FB_E_INVAL if a system has more than 8 bodies.  A planet
+ * whose heliocentric orbit is not bound stops its system with status
+ * FB_SYS_UNBOUND. */
+fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *o);
 
 /* Integrate every active system to t_end (Algorithm 1's destination time).
  * Fixed step (o->adaptive == 0): whole steps of dt, then one shortened step

@@ -15,7 +15,7 @@ enum Row { R_M = 0, R_X = 1, R_V = 4, R_A = 7, R_J = 10, R_COUNT = 13 };
 
 enum SysStatus {
     ST_ACTIVE = 0, ST_DONE = 1, ST_ENCOUNTER = 2, ST_EJECTED = 3,
-    ST_NONFINITE = 4, ST_STALLED = 5, ST_MAXSTEPS = 6
+    ST_NONFINITE = 4, ST_STALLED = 5, ST_MAXSTEPS = 6, ST_UNBOUND = 7
 };
 
 enum Mapping { MAP_SPL = 1, MAP_BPL = 2 };
@@ -24,6 +24,7 @@ constexpr int kMaxBodies = 16;
 constexpr int kMaxSplBodies = 10;      // plain system-per-lane instances exist for n <= 10
 constexpr int kMaxSplAdv = 5;          // ... with adaptive steps / stop rules for n <= 5
 constexpr int kMaxSplPersistent = 0;   // the body-per-lane fused class runs no system-per-lane tiles
+constexpr int kMaxMvsBodies = 8;       // MVS kernels (system per lane) exist for n <= 8
 
 // Device view of one homogeneous body-count bucket.  Per-slot arrays have
 // `pitch` entries; slots [0, count) hold systems.
@@ -103,8 +104,18 @@ hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos
                          double *vel, double *acc, double *jerk, double *t,
                          int *status, long long *steps, double *dt_next,
                          hipStream_t s);
-hipError_t launch_diag(const Bucket &B, double *energy, double *angmom,
+hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs_form,
                        hipStream_t s);
+// Mixed-variable symplectic integrator (n <= kMaxMvsBodies, system per
+// lane): conversion of a bucket to and from MVS form, fixed-step quanta, and
+// read-back of a bucket in MVS form as inertial positions and velocities.
+hipError_t launch_mvs_enter(const Bucket &B, hipStream_t s);
+hipError_t launch_mvs_leave(const Bucket &B, hipStream_t s);
+hipError_t launch_plain_mvs(const Bucket &B, int waves_per_group, const StepParams &P,
+                            hipStream_t s);
+hipError_t launch_unpack_mvs(const Bucket &B, const long long *orig_off, double *pos,
+                             double *vel, double *t, int *status, long long *steps,
+                             hipStream_t s);
 hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s);
 // FP64 FMA issue-ceiling probe: blocks x 256 lanes, iters x kFmaChains FMAs
 // per lane (kFmaChains = 16); out holds blocks x 256 doubles.

@@ -1232,8 +1232,12 @@ __global__ void k_unpack(Bucket B, const long long *__restrict__ orig_off, doubl
     if (dtn) dtn[o] = B.dtn[s];
 }
 
-// Energy (each pair once) and angular momentum about the origin.
 template <int N>
+__device__ __forceinline__ void from_mvs(const double (&m)[N], double (&x)[N][3], double (&v)[N][3]);
+
+// Energy (each pair once) and angular momentum about the origin, of a bucket
+// in inertial form or (MVS) in MVS form, converted first.
+template <int N, bool MVS>
 __global__ void k_diag(Bucket B, double *energy, double *angmom)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1241,6 +1245,8 @@ __global__ void k_diag(Bucket B, double *energy, double *angmom)
         return;
     double m[N], x[N][3], v[N][3];
     load_xv<N>(B, s, m, x, v);
+    if (MVS)
+        from_mvs<N>(m, x, v);
     double kin = 0.0, pot = 0.0, L0 = 0.0, L1 = 0.0, L2 = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -1273,6 +1279,388 @@ __global__ void k_count_active(Bucket B, int *count)
     const unsigned long long mask = __ballot(act);
     if ((threadIdx.x & 63) == 0 && mask)
         atomicAdd(count, __popcll(mask));
+}
+
+// ---------------------------------------------------------------------------
+// mixed-variable symplectic (MVS) integrator, Section 2.2.2
+// ---------------------------------------------------------------------------
+// The paper's five sub-steps (Cartesian drift half step, kick half step,
+// Keplerian drift step, kick half step, Cartesian drift half step) are the
+// democratic heliocentric splitting (Duncan, Levison & Lee 1998): planets
+// move on Kepler orbits about the star with mu = m0 in heliocentric
+// positions Q_i = x_i - x_0 and barycentric velocities V_i; kicks apply the
+// planet-planet forces only; the drift moves every Q_i by the star's reflex
+// motion, dt sum_j m_j V_j / m0, and the centre of mass by dt Vc.
+//
+// A bucket in MVS form keeps body 0's x and v rows for the centre of mass X
+// and its velocity Vc, body i's rows for Q_i and V_i, and the a rows for the
+// planet-planet accelerations at Q, which the next step's first kick reuses:
+// the drifts move all Q_i together, so the separations do not change.
+
+// (r, v) advanced by dt on its Kepler orbit about mu.  The change x of the
+// eccentric anomaly solves Kepler's equation in difference form,
+//   n dt = x - (1 - r0/a) sin x + (r.v / sqrt(mu a)) (1 - cos x),
+// by Newton iteration from x = n dt; Lagrange's f and g functions give the
+// new state.  The caller has checked 1/a > 0.  Returns false if the
+// iteration does not converge in kMvsNewtonMax steps.
+constexpr int kMvsNewtonMax = 50;
+
+__device__ __forceinline__ bool kepler_drift(const double mu, double (&r)[3], double (&v)[3],
+                                             const double dt)
+{
+    const double r2 = fma(r[2], r[2], fma(r[1], r[1], r[0] * r[0]));
+    const double v2 = fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0]));
+    const double rv = fma(r[2], v[2], fma(r[1], v[1], r[0] * v[0]));
+    const double r0 = sqrt(r2);
+    const double alpha = 2.0 / r0 - v2 / mu;
+    const double a = 1.0 / alpha;
+    const double sqmua = sqrt(mu * a);
+    const double nmot = sqmua * alpha * alpha;   // sqrt(mu / a^3)
+    const double ec = 1.0 - r0 * alpha;
+    const double es = rv / sqmua;
+    const double M = nmot * dt;
+    double x = M, s = 0.0, c = 1.0;
+    bool ok = false;
+    for (int it = 0; it < kMvsNewtonMax; ++it) {
+        sincos(x, &s, &c);
+        const double F = fma(-ec, s, x) + fma(es, 1.0 - c, -M);
+        const double dF = fma(es, s, fma(-ec, c, 1.0));
+        const double dx = F / dF;
+        x -= dx;
+        if (fabs(dx) <= 1e-15 * (1.0 + fabs(x))) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok)
+        return false;
+    sincos(x, &s, &c);
+    const double omc = 1.0 - c;
+    const double f = fma(-a / r0, omc, 1.0);
+    const double g = dt - (x - s) / nmot;
+    const double rn = a * fma(es, s, fma(-ec, c, 1.0));
+    const double fd = -sqmua * s / (rn * r0);
+    const double gd = fma(-a / rn, omc, 1.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double rk = r[k], vk = v[k];
+        r[k] = fma(f, rk, g * vk);
+        v[k] = fma(fd, rk, gd * vk);
+    }
+    return true;
+}
+
+// Planet-planet accelerations at heliocentric positions Q[1..N-1].
+template <int N>
+__device__ __forceinline__ void mvs_acc(const double (&m)[N], const double (&Q)[N][3],
+                                        double (&acc)[N][3])
+{
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+        acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) {
+            const double d0 = Q[j][0] - Q[i][0], d1 = Q[j][1] - Q[i][1], d2 = Q[j][2] - Q[i][2];
+            const double s = rsqrt_nr(fma(d2, d2, fma(d1, d1, d0 * d0)));
+            const double s3 = s * s * s;
+            const double mj = m[j] * s3, mi = m[i] * s3;
+            acc[i][0] = fma(mj, d0, acc[i][0]);
+            acc[i][1] = fma(mj, d1, acc[i][1]);
+            acc[i][2] = fma(mj, d2, acc[i][2]);
+            acc[j][0] = fma(-mi, d0, acc[j][0]);
+            acc[j][1] = fma(-mi, d1, acc[j][1]);
+            acc[j][2] = fma(-mi, d2, acc[j][2]);
+        }
+}
+
+// Drift of every Q_i by h sum_j m_j V_j / m0 and of X by h Vc (body 0's rows).
+template <int N>
+__device__ __forceinline__ void mvs_drift(const double (&m)[N], double (&Q)[N][3],
+                                          const double (&V)[N][3], const double inv_m0,
+                                          const double h)
+{
+    double P[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            P[c] = fma(m[i], V[i][c], P[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double dq = h * P[c] * inv_m0;
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+            Q[i][c] += dq;
+        Q[0][c] = fma(h, V[0][c], Q[0][c]);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void mvs_kick(double (&V)[N][3], const double (&acc)[N][3], const double h)
+{
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            V[i][c] = fma(h, acc[i][c], V[i][c]);
+}
+
+// One MVS step of h.  Returns ST_ACTIVE, or ST_UNBOUND when a planet's
+// heliocentric orbit is not bound (the half drift and kick are undone, so
+// the state is the step's start up to rounding) or Kepler's equation does not
+// converge (state of the planets drifted so far).
+template <int N>
+__device__ __forceinline__ int mvs_step(const double (&m)[N], double (&Q)[N][3], double (&V)[N][3],
+                                        double (&acc)[N][3], const double inv_m0, const double h)
+{
+    const double hh = 0.5 * h;
+    mvs_drift<N>(m, Q, V, inv_m0, hh);
+    mvs_kick<N>(V, acc, hh);
+    bool bound = true;
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        const double r2 = fma(Q[i][2], Q[i][2], fma(Q[i][1], Q[i][1], Q[i][0] * Q[i][0]));
+        const double v2 = fma(V[i][2], V[i][2], fma(V[i][1], V[i][1], V[i][0] * V[i][0]));
+        bound = bound && (2.0 / sqrt(r2) - v2 / m[0] > 0.0);
+    }
+    if (!bound) {
+        mvs_kick<N>(V, acc, -hh);
+        mvs_drift<N>(m, Q, V, inv_m0, -hh);
+        return ST_UNBOUND;
+    }
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+        if (!kepler_drift(m[0], Q[i], V[i], h))
+            return ST_UNBOUND;
+    mvs_acc<N>(m, Q, acc);
+    mvs_kick<N>(V, acc, hh);
+    mvs_drift<N>(m, Q, V, inv_m0, hh);
+    return ST_ACTIVE;
+}
+
+template <int N>
+__device__ __forceinline__ void load_rows(const Bucket &B, int s, double (&m)[N], double (&x)[N][3],
+                                          double (&v)[N][3], double (&a)[N][3], bool with_a)
+{
+    const size_t pitch = B.pitch;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        m[b] = B.st[(R_M * N + b) * pitch + s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[b][c] = B.st[((R_X + c) * N + b) * pitch + s];
+            v[b][c] = B.st[((R_V + c) * N + b) * pitch + s];
+            a[b][c] = with_a ? B.st[((R_A + c) * N + b) * pitch + s] : 0.0;
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void store_rows(const Bucket &B, int s, const double (&x)[N][3],
+                                           const double (&v)[N][3], const double (&a)[N][3],
+                                           bool with_a)
+{
+    const size_t pitch = B.pitch;
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            B.st[((R_X + c) * N + b) * pitch + s] = x[b][c];
+            B.st[((R_V + c) * N + b) * pitch + s] = v[b][c];
+            if (with_a)
+                B.st[((R_A + c) * N + b) * pitch + s] = a[b][c];
+        }
+}
+
+// Inertial (x, v) -> MVS form in place: X, Vc in row 0, Q_i = x_i - x_0,
+// V_i = v_i - Vc, and the planet-planet accelerations at Q.
+template <int N>
+__device__ __forceinline__ void to_mvs(const double (&m)[N], double (&x)[N][3], double (&v)[N][3])
+{
+    double M = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        M += m[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double sx = 0.0, sv = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            sx = fma(m[i], x[i][c], sx);
+            sv = fma(m[i], v[i][c], sv);
+        }
+        const double X = sx / M, Vc = sv / M, x0 = x[0][c];
+#pragma unroll
+        for (int i = 1; i < N; ++i) {
+            x[i][c] -= x0;
+            v[i][c] -= Vc;
+        }
+        x[0][c] = X;
+        v[0][c] = Vc;
+    }
+}
+
+// MVS form -> inertial in place: x_0 = X - sum m_i Q_i / M, x_i = x_0 + Q_i,
+// v_0 = Vc - sum m_i V_i / m0, v_i = Vc + V_i.
+template <int N>
+__device__ __forceinline__ void from_mvs(const double (&m)[N], double (&x)[N][3], double (&v)[N][3])
+{
+    double M = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        M += m[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double sq = 0.0, sp = 0.0;
+#pragma unroll
+        for (int i = 1; i < N; ++i) {
+            sq = fma(m[i], x[i][c], sq);
+            sp = fma(m[i], v[i][c], sp);
+        }
+        const double x0 = x[0][c] - sq / M, Vc = v[0][c];
+        x[0][c] = x0;
+        v[0][c] = Vc - sp / m[0];
+#pragma unroll
+        for (int i = 1; i < N; ++i) {
+            x[i][c] += x0;
+            v[i][c] += Vc;
+        }
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_mvs_enter(Bucket B)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3], a[N][3];
+    load_rows<N>(B, s, m, x, v, a, false);
+    to_mvs<N>(m, x, v);
+    mvs_acc<N>(m, x, a);
+    a[0][0] = a[0][1] = a[0][2] = 0.0;
+    store_rows<N>(B, s, x, v, a, true);
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_mvs_leave(Bucket B)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3], a[N][3];
+    load_rows<N>(B, s, m, x, v, a, false);
+    from_mvs<N>(m, x, v);
+    store_rows<N>(B, s, x, v, a, false);
+}
+
+// Fixed-step MVS integration of one system per lane for at most P.quantum
+// steps: the run's whole steps, then the shortened final step if one is due
+// (the clock logic of the Hermite kernels).
+template <int N>
+__global__ __launch_bounds__(256) void k_plain_mvs(Bucket B, StepParams P)
+{
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= B.count)
+        return;
+    Clock c = load_clock(B, slot);
+    if (c.status != ST_ACTIVE)
+        return;
+    double m[N], Q[N][3], V[N][3], acc[N][3];
+    load_rows<N>(B, slot, m, Q, V, acc, true);
+    const double inv_m0 = 1.0 / m[0];
+    int budget = P.quantum;
+#pragma unroll 1
+    for (int seg = 0; seg < 2 && c.status == ST_ACTIVE && budget > 0; ++seg) {
+        long long cnt = 0;
+        double h = c.dt;
+        if (seg == 0) {
+            cnt = c.nfull - c.k;
+            cnt = cnt < 0 ? 0 : cnt;
+        } else {
+            const double rem = c.t_end - c.t;
+            if (rem * c.dt > 1e-9 * c.dt * c.dt) {
+                cnt = 1;
+                h = rem;
+            } else {
+                c.t = c.t_end;
+                c.status = ST_DONE;
+            }
+        }
+        cnt = min(cnt, (long long)budget);
+        cnt = min(cnt, P.max_steps - c.steps);
+        const int nrun = cnt > 0 ? (int)cnt : 0;
+        int done = 0;
+#pragma unroll 1
+        for (; done < nrun; ++done) {
+            const int st = mvs_step<N>(m, Q, V, acc, inv_m0, h);
+            if (st != ST_ACTIVE) {
+                c.status = st;
+                break;
+            }
+        }
+        budget -= done;
+        c.steps += done;
+        if (seg == 0) {
+            c.k += done;
+            if (done > 0)
+                c.t = fma((double)c.k, c.dt, c.t0);
+            if (c.status == ST_ACTIVE && c.k >= c.nfull) {
+                const double rem = c.t_end - c.t;
+                if (!(rem * c.dt > 1e-9 * c.dt * c.dt)) {
+                    c.t = c.t_end;
+                    c.status = ST_DONE;
+                }
+            }
+        } else if (done > 0 && c.status == ST_ACTIVE) {
+            c.t = c.t_end;
+            c.status = ST_DONE;
+        }
+        if (c.status == ST_ACTIVE && c.steps >= P.max_steps)
+            c.status = ST_MAXSTEPS;
+    }
+    bool fin = true;
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+        fin = fin && finite3(Q[b]) && finite3(V[b]);
+    if (!fin)
+        c.status = ST_NONFINITE;
+    store_rows<N>(B, slot, Q, V, acc, true);
+    store_clock(B, slot, c);
+}
+
+// State read-back of a bucket in MVS form: converted to inertial (x, v) on
+// the way out; the stored form is left as it is.
+template <int N>
+__global__ __launch_bounds__(64) void k_unpack_mvs(Bucket B, const long long *__restrict__ orig_off,
+                                                   double *pos, double *vel, double *t, int *status,
+                                                   long long *steps)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3], a[N][3];
+    load_rows<N>(B, s, m, x, v, a, false);
+    from_mvs<N>(m, x, v);
+    const int o = B.orig[s];
+    const long long base = orig_off[o];
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (pos)
+                pos[3 * (base + b) + c] = x[b][c];
+            if (vel)
+                vel[3 * (base + b) + c] = v[b][c];
+        }
+    if (t)
+        t[o] = B.t[s];
+    if (status)
+        status[o] = B.status[s];
+    if (steps)
+        steps[o] = B.steps[s];
 }
 
 // FP64 issue-ceiling probe for the roofline: each lane runs kFmaChains
@@ -1483,12 +1871,75 @@ hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos
     return hipGetLastError();
 }
 
-hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, hipStream_t s)
+hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs_form,
+                       hipStream_t s)
 {
     if (B.count == 0)
         return hipSuccess;
-#define FB_L(NN) hipLaunchKernelGGL(k_diag<NN>, grid_for(B.count, 64), dim3(64), 0, s, B, energy, angmom)
-    FB_SWITCH_N(B.n, FB_L)
+    if (mvs_form) {
+        if (B.n > kMaxMvsBodies)
+            return hipErrorInvalidValue;
+#define FB_L(NN) hipLaunchKernelGGL((k_diag<NN, true>), grid_for(B.count, 64), dim3(64), 0, s, B, energy, angmom)
+        FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    } else {
+#define FB_L(NN) hipLaunchKernelGGL((k_diag<NN, false>), grid_for(B.count, 64), dim3(64), 0, s, B, energy, angmom)
+        FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    }
+    return hipGetLastError();
+}
+
+#define FB_SWITCH_MVS(n, MACRO)                                                         \
+    switch (n) {                                                                        \
+    case 2: MACRO(2); break;  case 3: MACRO(3); break;  case 4: MACRO(4); break;        \
+    case 5: MACRO(5); break;  case 6: MACRO(6); break;  case 7: MACRO(7); break;        \
+    case 8: MACRO(8); break;                                                            \
+    default: return hipErrorInvalidValue;                                               \
+    }
+static_assert(kMaxMvsBodies == 8, "FB_SWITCH_MVS covers n = 2..kMaxMvsBodies");
+
+hipError_t launch_mvs_enter(const Bucket &B, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN) hipLaunchKernelGGL(k_mvs_enter<NN>, grid_for(B.count, 64), dim3(64), 0, s, B)
+    FB_SWITCH_MVS(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+hipError_t launch_mvs_leave(const Bucket &B, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN) hipLaunchKernelGGL(k_mvs_leave<NN>, grid_for(B.count, 64), dim3(64), 0, s, B)
+    FB_SWITCH_MVS(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_mvs(const Bucket &B, int waves_per_group, const StepParams &P,
+                            hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+    const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
+    const dim3 grid = grid_for(B.count, 64 * W);
+#define FB_L(NN) hipLaunchKernelGGL(k_plain_mvs<NN>, grid, dim3(64 * W), 0, s, B, P)
+    FB_SWITCH_MVS(B.n, FB_L)
+#undef FB_L
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_mvs(const Bucket &B, const long long *orig_off, double *pos, double *vel,
+                             double *t, int *status, long long *steps, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN) hipLaunchKernelGGL(k_unpack_mvs<NN>, grid_for(B.count, 64), dim3(64), 0, s, B, \
+                                    orig_off, pos, vel, t, status, steps)
+    FB_SWITCH_MVS(B.n, FB_L)
 #undef FB_L
     return hipGetLastError();
 }

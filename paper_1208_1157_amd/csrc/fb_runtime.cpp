@@ -247,6 +247,7 @@ struct fb_ensemble {
     int *d_mapping = nullptr;
     int *h_pinned = nullptr;        // pinned host ints for control reads
     hipStream_t capture_stream = nullptr;
+    bool mvs_form = false;          // state rows hold the MVS variables, not (x, v, a0, j0)
 };
 
 namespace {
@@ -571,6 +572,38 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     return result;
 }
 
+// Back from MVS form to the Hermite state: inertial (x, v) and a fresh
+// set-up evaluation of (a0, j0).
+fb_status ensure_inertial(fb_ensemble *e)
+{
+    if (!e->mvs_form)
+        return FB_OK;
+    for (const Bucket &B : e->buckets) {
+        FB_HIP(launch_mvs_leave(B, e->stream));
+        FB_HIP(launch_prepare(B, e->stream));
+    }
+    e->mvs_form = false;
+    return FB_OK;
+}
+
+// MVS quanta: one system-per-lane launch per bucket and quantum.
+fb_status run_mvs(fb_ensemble *e, const fb_opts &o, long long step_bound)
+{
+    const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
+    for (;;) {
+        for (const Bucket &B : e->buckets) {
+            const StepParams P = make_params(o, quantum);
+            ProfScope ps(e->stream);
+            FB_HIP(launch_plain_mvs(B, 1, P, e->stream));
+        }
+        if (quantum == INT_MAX)
+            return FB_OK;
+        step_bound -= quantum;
+        if (step_bound <= 0)
+            return FB_OK;
+    }
+}
+
 fb_status run(fb_ensemble *e, const fb_opts &o, long long step_bound)
 {
     if (o.schedule == FB_SCHED_PERSISTENT)
@@ -724,9 +757,46 @@ fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt, const f
         return st;
     if (n_steps == 0 || e->n_sys == 0)
         return FB_OK;
+    st = ensure_inertial(e);
+    if (st != FB_OK)
+        return st;
     for (const Bucket &B : e->buckets)
         FB_HIP(launch_begin_run(B, 1, n_steps, 0.0, dt, 0, 0.0, e->stream));
     return run(e, o, o.stop_rules ? -1 : n_steps);
+}
+
+fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *po)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    if (o.adaptive || o.stop_rules || o.compact || o.schedule != FB_SCHED_PLAIN)
+        return fail(FB_E_INVAL, "MVS takes fixed steps on the plain schedule without stop rules "
+                                "(opts.adaptive, stop_rules and compact must be 0, schedule plain)");
+    fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    if (n_steps < 0)
+        return fail(FB_E_INVAL, "n_steps must be >= 0");
+    if (!(std::isfinite(dt) && dt != 0.0))
+        return fail(FB_E_INVAL, "dt must be finite and non-zero");
+    for (const Bucket &B : e->buckets)
+        if (B.n > kMaxMvsBodies)
+            return fail(FB_E_INVAL, "MVS is built for systems of at most %d bodies (got %d)",
+                        kMaxMvsBodies, B.n);
+    if (n_steps == 0 || e->n_sys == 0)
+        return FB_OK;
+    if (!e->mvs_form) {
+        for (const Bucket &B : e->buckets)
+            FB_HIP(launch_mvs_enter(B, e->stream));
+        e->mvs_form = true;
+    }
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_begin_run(B, 1, n_steps, 0.0, dt, 0, 0.0, e->stream));
+    return run_mvs(e, o, n_steps);
 }
 
 fb_status fb_integrate(fb_ensemble *e, double t_end, double dt, const fb_opts *po)
@@ -746,6 +816,9 @@ fb_status fb_integrate(fb_ensemble *e, double t_end, double dt, const fb_opts *p
         return fail(FB_E_INVAL, "dt must be finite and non-zero");
     if (e->n_sys == 0)
         return FB_OK;
+    st = ensure_inertial(e);
+    if (st != FB_OK)
+        return st;
     for (const Bucket &B : e->buckets)
         FB_HIP(launch_begin_run(B, 0, 0, t_end, dt, o.adaptive == 2 ? 2 : (o.adaptive ? 1 : 0),
                                 o.eta, e->stream));
@@ -771,10 +844,16 @@ fb_status fb_get_state(fb_ensemble *e, double *pos, double *vel, double *t, int3
     double *d_pos = e->d_staging, *d_vel = d_pos + 3 * N, *d_t = d_vel + 3 * N;
     long long *d_steps = (long long *)(d_t + ns);
     int *d_status = (int *)(d_steps + ns);
-    for (const Bucket &B : e->buckets)
-        FB_HIP(launch_unpack(B, e->d_orig_off, pos ? d_pos : nullptr, vel ? d_vel : nullptr,
-                             nullptr, nullptr, t ? d_t : nullptr, status ? d_status : nullptr,
-                             steps ? d_steps : nullptr, nullptr, e->stream));
+    for (const Bucket &B : e->buckets) {
+        if (e->mvs_form)
+            FB_HIP(launch_unpack_mvs(B, e->d_orig_off, pos ? d_pos : nullptr, vel ? d_vel : nullptr,
+                                     t ? d_t : nullptr, status ? d_status : nullptr,
+                                     steps ? d_steps : nullptr, e->stream));
+        else
+            FB_HIP(launch_unpack(B, e->d_orig_off, pos ? d_pos : nullptr, vel ? d_vel : nullptr,
+                                 nullptr, nullptr, t ? d_t : nullptr, status ? d_status : nullptr,
+                                 steps ? d_steps : nullptr, nullptr, e->stream));
+    }
     if (pos)
         FB_HIP(hipMemcpyAsync(pos, d_pos, 24 * N, hipMemcpyDeviceToHost, e->stream));
     if (vel)
@@ -793,6 +872,9 @@ fb_status fb_get_hermite_state(fb_ensemble *e, double *acc0, double *jerk0, doub
 {
     if (!e)
         return fail(FB_E_INVAL, "ensemble is NULL");
+    if (e->mvs_form)
+        return fail(FB_E_STATE, "the ensemble holds MVS state; a Hermite integration restores "
+                                "(a0, j0)");
     const size_t N = (size_t)e->L.n_bodies, ns = (size_t)e->n_sys;
     if (ns == 0)
         return FB_OK;
@@ -820,7 +902,7 @@ fb_status fb_diagnostics(fb_ensemble *e, double *energy, double *angmom)
         return FB_OK;
     double *d_E = e->d_diag, *d_L = d_E + ns;
     for (const Bucket &B : e->buckets)
-        FB_HIP(launch_diag(B, d_E, d_L, e->stream));
+        FB_HIP(launch_diag(B, d_E, d_L, e->mvs_form, e->stream));
     if (energy)
         FB_HIP(hipMemcpyAsync(energy, d_E, 8 * ns, hipMemcpyDeviceToHost, e->stream));
     if (angmom)
@@ -899,6 +981,9 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         *n_out = 0;
     if (e->n_sys == 0)
         return FB_OK;
+    fb_status st0 = ensure_inertial(e);
+    if (st0 != FB_OK)
+        return st0;
     const size_t total = e->L.total;
     char *backup = nullptr;
     FB_HIP(hipStreamSynchronize(e->stream));

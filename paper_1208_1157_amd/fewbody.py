@@ -30,7 +30,8 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_BUDGET, E_STATE, E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
-ACTIVE, DONE, ENCOUNTER, EJECTED, NONFINITE, STALLED_DT, MAXSTEPS = range(7)
+ACTIVE, DONE, ENCOUNTER, EJECTED, NONFINITE, STALLED_DT, MAXSTEPS, UNBOUND = range(8)
+MAX_MVS_BODIES = 8
 STOP_ENCOUNTER, STOP_EJECT = 1, 2
 MAP_AUTO, MAP_SPL, MAP_BPL = 0, 1, 2
 SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
@@ -77,6 +78,7 @@ _SIGS = {
     "fb_ensemble_create_device": (ctypes.c_int, [_i32, _p, _p, _p, _p, _p, _p, _sz, _p,
                                                  ctypes.POINTER(_p)]),
     "fb_integrate_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
+    "fb_integrate_mvs": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate": (ctypes.c_int, [_p, _d, _d, ctypes.POINTER(FbOpts)]),
     "fb_synchronize": (ctypes.c_int, [_p]),
     "fb_get_state": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
@@ -248,6 +250,12 @@ class Ensemble:
     def integrate_steps(self, n_steps, dt, opts: Opts | None = None):
         o = (opts or Opts()).c()
         _check(_lib.fb_integrate_steps(self._handle, int(n_steps), float(dt), ctypes.byref(o)))
+
+    def integrate_mvs(self, n_steps, dt, opts: Opts | None = None):
+        """n_steps fixed steps of the mixed-variable symplectic integrator
+        (fb_integrate_mvs; systems of at most MAX_MVS_BODIES bodies)."""
+        o = (opts or Opts()).c()
+        _check(_lib.fb_integrate_mvs(self._handle, int(n_steps), float(dt), ctypes.byref(o)))
 
     def integrate(self, t_end, dt=0.0, opts: Opts | None = None):
         o = (opts or Opts()).c()

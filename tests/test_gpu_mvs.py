@@ -1,0 +1,202 @@
+"""The mixed-variable symplectic (MVS) kernels against the MVS oracle:
+parity on ragged ensembles of 2..8 bodies and on a sampled full-size
+ensemble, bitwise independence of call chunking, exact Kepler motion of
+massless planets, hand-over to the Hermite integrator, diagnostics in MVS
+form, unbound planets and argument checks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_1157_amd import gen
+from tests.helpers import REL_TOL, per_system_rel_err
+from tests.test_oracle_mvs import elements_propagate, orbit
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2 * math.pi
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def mixed_ensemble():
+    parts = [gen.ragged_hill(150, seed=41, n_lo=2, n_hi=8),
+             gen.paper_ics(5, 3), gen.paper_ics(5, 4), gen.three_body(70, seed=42)]
+    nb = np.concatenate([p.n_body for p in parts])
+    return gen.Ensemble(nb, np.concatenate([p.mass for p in parts]), np.concatenate([p.pos for p in parts]),
+                        np.concatenate([p.vel for p in parts]))
+
+
+def oracle_mvs(ora, ens, dt, nsteps, systems=None):
+    idx = range(ens.n_sys) if systems is None else systems
+    out = {}
+    for s in idx:
+        out[s] = ora.integrate_mvs(*ens.system(s), dt, nsteps)
+    return out
+
+
+def check_parity(ora, fb, ens, st, ref):
+    off = ens.offsets
+    worst = 0.0
+    for s, o in ref.items():
+        assert o["status"] == ora.DONE and st["status"][s] == fb.DONE, (s, o["status"], st["status"][s])
+        sl = slice(off[s], off[s + 1])
+        ex = per_system_rel_err([ens.n_body[s]], st["pos"][sl], o["pos"])[0]
+        ev = per_system_rel_err([ens.n_body[s]], st["vel"][sl], o["vel"])[0]
+        worst = max(worst, ex, ev)
+        assert ex <= REL_TOL and ev <= REL_TOL, (s, int(ens.n_body[s]), ex, ev)
+    return worst
+
+
+def test_parity_ragged_2_to_8(fb, ora):
+    ens = mixed_ensemble()
+    dt, nsteps = TWO_PI / 100, 300
+    say("MVS parity", ens.n_sys, "systems")
+    E = fb.from_gen(ens)
+    E.integrate_mvs(nsteps, dt)
+    st = E.state()
+    E.close()
+    assert np.all(st["steps"] == nsteps)
+    assert np.allclose(st["t"], nsteps * dt, rtol=0, atol=1e-12)
+    worst = check_parity(ora, fb, ens, st, oracle_mvs(ora, ens, dt, nsteps))
+    say("worst rel err", worst)
+
+
+def test_full_size_sampled_parity(fb, ora):
+    ens, _ = gen.workload("homog_131072x3")
+    dt, nsteps = TWO_PI / 100, 1000
+    say("MVS full size", ens.n_sys)
+    E = fb.from_gen(ens)
+    E.integrate_mvs(nsteps, dt)
+    st = E.state()
+    E.close()
+    sample = np.random.default_rng(0).choice(ens.n_sys, 192, replace=False)
+    check_parity(ora, fb, ens, st, oracle_mvs(ora, ens, dt, nsteps, sample))
+
+
+def test_chunking_is_bitwise_invisible(fb):
+    ens = gen.ragged_hill(200, seed=43, n_lo=3, n_hi=8)
+    dt = TWO_PI / 80
+    say("MVS chunking")
+    E1 = fb.from_gen(ens)
+    E1.integrate_mvs(240, dt)
+    a = E1.state()
+    E1.close()
+    E2 = fb.from_gen(ens)
+    for _ in range(3):
+        E2.integrate_mvs(80, dt, fb.Opts(steps_per_quantum=27))
+        E2.state()                       # read-back leaves the MVS state untouched
+    b = E2.state()
+    E2.close()
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    assert np.array_equal(a["steps"], b["steps"])
+
+
+@pytest.mark.parametrize("dt_frac", [0.004, 0.13])
+def test_massless_planets_exact(fb, dt_frac):
+    """Massless planets: exact Kepler orbits about a star at rest, compared
+    with the independent elements-and-bisection route."""
+    els = [(1.0, 0.1, 0.02, 0.3, 0.5, 0.1), (1.6, 0.4, 0.2, 1.0, 2.0, 3.0), (2.9, 0.05, 0.1, 4.0, 0.2, 5.5)]
+    n = len(els) + 1
+    reps = 64
+    m = np.tile(np.array([1.0] + [0.0] * len(els)), reps)
+    x = np.zeros((n * reps, 3))
+    v = np.zeros((n * reps, 3))
+    for k, el in enumerate(els):
+        r0, v0 = orbit(1.0, *el)
+        x[k + 1::n] = r0
+        v[k + 1::n] = v0
+    ens = gen.Ensemble(np.full(reps, n, dtype=np.int32), m, x, v)
+    dt, nsteps = dt_frac * TWO_PI, 60
+    say("massless", dt_frac)
+    E = fb.from_gen(ens)
+    E.integrate_mvs(nsteps, dt)
+    st = E.state()
+    E.close()
+    for k in range(len(els)):
+        re, ve = elements_propagate(x[k + 1], v[k + 1], 1.0, dt * nsteps)
+        assert np.abs(st["pos"][k + 1::n] - re).max() < 1e-11
+        assert np.abs(st["vel"][k + 1::n] - ve).max() < 1e-11
+    assert np.abs(st["pos"][0::n]).max() == 0.0
+
+
+def test_hand_over_to_hermite(fb, ora):
+    """MVS, then Hermite: the Hermite run starts from the converted state with
+    a fresh set-up evaluation, as the oracle does."""
+    ens = gen.ragged_hill(40, seed=44, n_lo=3, n_hi=6)
+    dt_m, dt_h = TWO_PI / 100, TWO_PI / 1000
+    say("MVS then Hermite")
+    E = fb.from_gen(ens)
+    E.integrate_mvs(100, dt_m)
+    with pytest.raises(fb.FewbodyError) as ei:
+        E.hermite_state()
+    assert ei.value.code == fb.E_STATE
+    E.integrate_steps(200, dt_h)
+    st = E.state()
+    E.close()
+    off = ens.offsets
+    for s in range(ens.n_sys):
+        o = ora.integrate_mvs(*ens.system(s), dt_m, 100)
+        x, v, _, _ = ora.integrate_fixed(ens.system(s)[0], o["pos"], o["vel"], dt_h, 200)
+        sl = slice(off[s], off[s + 1])
+        assert per_system_rel_err([ens.n_body[s]], st["pos"][sl], x)[0] <= REL_TOL
+        assert per_system_rel_err([ens.n_body[s]], st["vel"][sl], v)[0] <= REL_TOL
+
+
+def test_diagnostics_in_mvs_form(fb, ora):
+    ens = gen.ragged_hill(64, seed=45, n_lo=3, n_hi=8)
+    dt = TWO_PI / 100
+    E = fb.from_gen(ens)
+    E0, L0 = E.diagnostics()
+    E.integrate_mvs(150, dt)
+    E1, L1 = E.diagnostics()
+    st = E.state()
+    E.close()
+    off = ens.offsets
+    for s in range(ens.n_sys):
+        sl = slice(off[s], off[s + 1])
+        e_ora, l_ora = ora.energy(ens.system(s)[0], st["pos"][sl], st["vel"][sl])
+        assert abs(E1[s] - e_ora) <= 1e-12 * abs(e_ora)
+        assert np.abs(L1[s] - l_ora).max() <= 1e-12 * np.abs(l_ora).max()
+    # symplectic and momentum-exact: small energy error, angular momentum kept
+    assert np.max(np.abs(E1 / E0 - 1)) < 1e-4
+    assert np.max(np.abs(L1 - L0)) < 1e-12 * np.abs(L0).max()
+
+
+def test_unbound_planet_stops_its_system(fb, ora):
+    good = gen.three_body(3, seed=46)
+    m = np.array([1.0, 1e-4, 1e-4])
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, 2.0, 0]])
+    v = np.array([[0.0, 0, 0], [0, 1.6, 0], [-0.7, 0, 0]])     # planet 1 beyond escape speed
+    ens = gen.Ensemble(np.concatenate([good.n_body, [3]]).astype(np.int32),
+                       np.concatenate([good.mass, m]), np.concatenate([good.pos, x]),
+                       np.concatenate([good.vel, v]))
+    dt = TWO_PI / 100
+    E = fb.from_gen(ens)
+    E.integrate_mvs(50, dt)
+    st = E.state()
+    E.close()
+    o = ora.integrate_mvs(m, x, v, dt, 50)
+    assert o["status"] == ora.UNBOUND and o["steps"] == 0
+    assert st["status"][3] == fb.UNBOUND and st["steps"][3] == 0
+    assert np.abs(st["pos"][9:12] - x).max() < 1e-14 and np.abs(st["vel"][9:12] - v).max() < 1e-14
+    assert np.all(st["status"][:3] == fb.DONE)
+
+
+def test_argument_checks(fb):
+    big = gen.ragged_hill(4, seed=47, n_lo=9, n_hi=9)
+    E = fb.from_gen(big)
+    with pytest.raises(fb.FewbodyError) as ei:
+        E.integrate_mvs(10, 0.01)
+    assert ei.value.code == fb.E_INVAL
+    E.close()
+    E = fb.from_gen(gen.three_body(4, seed=48))
+    for opts in (fb.Opts(adaptive=True), fb.Opts(stop_rules=1), fb.Opts(schedule=fb.SCHED_PERSISTENT)):
+        with pytest.raises(fb.FewbodyError) as ei:
+            E.integrate_mvs(10, 0.01, opts)
+        assert ei.value.code == fb.E_INVAL
+    with pytest.raises(fb.FewbodyError):
+        E.integrate_mvs(10, 0.0)
+    E.close()
