@@ -23,7 +23,8 @@ Printed as one JSON line, with
                 uneven lifetimes 65536 x (4..8) with adaptive steps and stop
                 rules on a bounded horizon, plain launches vs persistent
                 quanta with compaction; Section 5.1's initial conditions at
-                Table 3's size, beside the paper's times.
+                Table 3's size, beside the paper's times; the MVS integrator
+                on the headline ensemble and the Section 5.1 systems.
 """
 from __future__ import annotations
 
@@ -209,6 +210,29 @@ def paper_ic_extras(fb, gen, torch, log, n_sys=131072, h=1e-3, t_end=1.0):
             "rows": rows}
 
 
+def mvs_extras(fb, gen, torch, log, dt=1e-2, steps=20000):
+    """The mixed-variable symplectic integrator (Section 2.2.3) at the paper's
+    step for it (Section 5.2.2: dt = 1e-2): the headline ensemble for `steps`
+    steps, and Section 5.1's initial conditions at 131072 systems for one
+    time unit.  Work unit: system-steps (each planet takes one Kepler drift,
+    every planet pair one acceleration evaluation)."""
+    out = {"dt": dt}
+    ens, _ = gen.workload("homog_131072x3")
+    t, st = timed(fb, torch, ens, lambda E: E.integrate_mvs(steps, dt))
+    assert (st["status"] == fb.DONE).all()
+    out["homog_131072x3"] = {"steps": steps, "seconds": t, "system_steps_per_s": ens.n_sys * steps / t}
+    log(f"[bench] MVS homog_131072x3: {ens.n_sys * steps / t:.3e} system-steps/s")
+    rows = []
+    n_steps = int(round(1.0 / dt))
+    for n in (3, 4, 5, 6, 8):
+        e = gen.paper_ics(131072, n)
+        t, st = timed(fb, torch, e, lambda E: E.integrate_mvs(n_steps, dt))
+        assert (st["status"] == fb.DONE).all()
+        rows.append({"n": n, "seconds": t, "system_steps_per_s": e.n_sys * n_steps / t})
+    out["paper_ics_one_time_unit"] = rows
+    return out
+
+
 def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, policy="srpt",
                    cls="spl", quantum_tiles=0, long_steps=300000):
     from paper_1208_1157_amd import serve
@@ -379,6 +403,7 @@ def main():
         extras["lifetimes"] = lifetimes_extras(fb, gen, torch, log, orbits=args.lifetimes_orbits)
         restore_plans()
         extras["paper_ics"] = paper_ic_extras(fb, gen, torch, log)
+        extras["mvs"] = mvs_extras(fb, gen, torch, log)
     if extras:
         result["extras"] = extras
     if not args.no_cpu:

@@ -154,7 +154,7 @@ fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body,
 fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
                              const fb_opts *o);
 
-/* Mixed-variable symplectic integration (Section 2.2.2) of every active
+/* Mixed-variable symplectic integration (Section 2.2.3) of every active
  * system by exactly n_steps fixed steps of dt, for systems of at most 8
  * bodies (body 0 the central star).  Each step is the paper's sequence of
  * sub-steps: Cartesian drift dt/2, kick dt/2, Keplerian drift dt, kick dt/2,

@@ -1,11 +1,11 @@
 /* mvs_oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow FP64 reference of the mixed-variable symplectic (MVS)
- * integrator of Section 2.2.2, for checking the HIP kernels.  Only the test
+ * integrator of Section 2.2.3, for checking the HIP kernels.  Only the test
  * suite, the smoke check and the benchmark's CPU-baseline leg may load it;
  * the product library never does, and the two share no code.
  *
- * The five sub-steps of Section 2.2.2 (Cartesian drift half step, kick half
+ * The five sub-steps of Section 2.2.3 (Cartesian drift half step, kick half
  * step, Keplerian drift step, kick half step, Cartesian drift half step) are
  * the democratic heliocentric splitting of the N-body Hamiltonian (Duncan,
  * Levison & Lee 1998), with G = 1:
@@ -18,8 +18,9 @@
  *              barycentric velocity is -sum_j m_j V_j / m_0, so every
  *              heliocentric Q_i moves by dt sum_j m_j V_j / m_0).
  * The kick evaluates the planet-planet accelerations at the current
- * positions every time (the paper reuses the previous step's values, which
- * are equal up to rounding because the drifts move all Q_i together).
+ * positions every time.  The paper reuses the previous step's values
+ * (Section 4.3.3); they are equal up to rounding, because the drifts move
+ * all Q_i together.
  *
  * Kepler drift: for a bound orbit (1/a = 2/|r| - |v|^2/mu > 0) the change of
  * eccentric anomaly x over dt solves Kepler's equation in difference form

@@ -1282,7 +1282,7 @@ __global__ void k_count_active(Bucket B, int *count)
 }
 
 // ---------------------------------------------------------------------------
-// mixed-variable symplectic (MVS) integrator, Section 2.2.2
+// mixed-variable symplectic (MVS) integrator, Sections 2.2.3 and 4.3.3
 // ---------------------------------------------------------------------------
 // The paper's five sub-steps (Cartesian drift half step, kick half step,
 // Keplerian drift step, kick half step, Cartesian drift half step) are the

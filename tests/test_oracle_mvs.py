@@ -1,4 +1,4 @@
-"""Pins of the MVS oracle (Section 2.2.2's mixed-variable symplectic
+"""Pins of the MVS oracle (Section 2.2.3's mixed-variable symplectic
 integrator) against facts that do not come from it: Kepler orbits through
 the classical elements with Kepler's equation solved by bisection, rigid
 rotation of circular orbits, the group properties of a Kepler flow,
