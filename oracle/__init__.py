@@ -1,7 +1,7 @@
 """CPU oracle for the fewbody integrators -- TEST INFRASTRUCTURE ONLY.
 
-A ctypes wrapper around ``hermite_oracle.c`` and ``mvs_oracle.c`` (plain FP64
-C, built with ``-O2 -ffp-contract=off``).  Only the test suite, the smoke check and the
+A ctypes wrapper around ``hermite_oracle.c``, ``mvs_oracle.c`` and
+``rkck_oracle.c`` (plain FP64 C, built with ``-O2 -ffp-contract=off``).  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package; the product library
 never does.  It shares no code with the HIP path: the only inputs both sides
 see come from the seeded generators.
@@ -18,7 +18,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "hermite_oracle.c"), os.path.join(HERE, "mvs_oracle.c")]
+SRCS = [os.path.join(HERE, "hermite_oracle.c"), os.path.join(HERE, "mvs_oracle.c"),
+        os.path.join(HERE, "rkck_oracle.c")]
 LIB = os.environ.get("FEWBODY_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 ACTIVE, DONE, ENCOUNTER, EJECTED, NONFINITE, STALLED_DT, MAXSTEPS, UNBOUND = range(8)
@@ -73,6 +74,14 @@ def lib():
         L.ora_mvs_step.restype = i
         L.ora_integrate_mvs.argtypes = [i, p, p, p, d, l, p]
         L.ora_integrate_mvs.restype = i
+        L.ora_rk_acc.argtypes = [i, p, p, p]
+        L.ora_rkck_step.argtypes = [i, p, p, p, d, p, p, p, p]
+        L.ora_integrate_rkck_fixed.argtypes = [i, p, p, p, d, l]
+        L.ora_integrate_rkck_fixed.restype = i
+        L.ora_rkck_error_norm.argtypes = [i, p, p, p, p, d]
+        L.ora_rkck_error_norm.restype = d
+        L.ora_integrate_rkck_adaptive.argtypes = [i, p, p, p, p, d, d, p, l, p, p]
+        L.ora_integrate_rkck_adaptive.restype = i
         _lib = L
     return _lib
 
@@ -273,3 +282,58 @@ def integrate_mvs(mass, pos, vel, dt, nsteps):
     done = ctypes.c_long()
     st = lib().ora_integrate_mvs(n, _p(m), _p(x), _p(v), float(dt), int(nsteps), ctypes.byref(done))
     return {"pos": x, "vel": v, "status": st, "steps": done.value}
+
+
+# ---------------------------------------------------------------- RKCK
+def rk_acc(mass, pos):
+    m = _f64(mass)
+    n = m.shape[0]
+    x = _f64(pos, (n, 3))
+    a = np.zeros((n, 3))
+    lib().ora_rk_acc(n, _p(m), _p(x), _p(a))
+    return a
+
+
+def rkck_step(mass, pos, vel, h):
+    """One Cash-Karp step: (x5, v5, err_x, err_v)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)), _f64(vel, (n, 3))
+    x5, v5, ex, ev = (np.zeros((n, 3)) for _ in range(4))
+    lib().ora_rkck_step(n, _p(m), _p(x), _p(v), float(h), _p(x5), _p(v5), _p(ex), _p(ev))
+    return x5, v5, ex, ev
+
+
+def rkck_error_norm(pos, vel, err_x, err_v, eps):
+    x = _f64(pos).reshape(-1, 3)
+    n = x.shape[0]
+    v, ex, ev = _f64(vel, (n, 3)), _f64(err_x, (n, 3)), _f64(err_v, (n, 3))
+    return float(lib().ora_rkck_error_norm(n, _p(x), _p(v), _p(ex), _p(ev), float(eps)))
+
+
+def integrate_rkck_fixed(mass, pos, vel, h, nsteps):
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)).copy(), _f64(vel, (n, 3)).copy()
+    st = lib().ora_integrate_rkck_fixed(n, _p(m), _p(x), _p(v), float(h), int(nsteps))
+    if st < 0:
+        raise ValueError("oracle rejected arguments")
+    return {"pos": x, "vel": v, "status": st}
+
+
+def integrate_rkck_adaptive(mass, pos, vel, t_end, eps, dt, t0=0.0, max_steps=10**9):
+    """Adaptive Cash-Karp to t_end from t0 with first trial step dt; returns
+    dict(pos, vel, t, status, steps, rejects, dt_next)."""
+    m = _f64(mass)
+    n = m.shape[0]
+    x, v = _f64(pos, (n, 3)).copy(), _f64(vel, (n, 3)).copy()
+    t = ctypes.c_double(t0)
+    h = ctypes.c_double(dt)
+    steps, rej = ctypes.c_long(), ctypes.c_long()
+    st = lib().ora_integrate_rkck_adaptive(n, _p(m), _p(x), _p(v), ctypes.byref(t), float(t_end),
+                                           float(eps), ctypes.byref(h), int(max_steps),
+                                           ctypes.byref(steps), ctypes.byref(rej))
+    if st < 0:
+        raise ValueError("oracle rejected arguments")
+    return {"pos": x, "vel": v, "t": t.value, "status": st, "steps": steps.value,
+            "rejects": rej.value, "dt_next": h.value}

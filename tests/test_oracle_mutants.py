@@ -3,7 +3,9 @@
 Each mutant is a plausible slip (a misread coefficient, a dropped power of
 h, a wrong sign, a swapped mass index, a double-counted pair, the star added
 first; for MVS a wrong Kepler mu, a dropped or reversed reflex drift, a
-whole kick, the star in the kick, a wrong f function, a wrong mass).  The
+whole kick, the star in the kick, a wrong f function, a wrong mass; for
+Cash-Karp a misread tableau entry, stale stage velocities, a loose
+acceptance test).  The
 copy is compiled into a temporary library and the pin suite of the mutated
 source is run against it in a subprocess; every mutant must make at least
 one pin fail, and the unmutated copy must pass.
@@ -16,8 +18,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = {"hermite": os.path.join(ROOT, "oracle", "hermite_oracle.c"),
-           "mvs": os.path.join(ROOT, "oracle", "mvs_oracle.c")}
-PINS = {"hermite": "test_oracle_pins.py", "mvs": "test_oracle_mvs.py"}
+           "mvs": os.path.join(ROOT, "oracle", "mvs_oracle.c"),
+           "rkck": os.path.join(ROOT, "oracle", "rkck_oracle.c")}
+PINS = {"hermite": "test_oracle_pins.py", "mvs": "test_oracle_mvs.py", "rkck": "test_oracle_rkck.py"}
 
 # name -> (source, text, replacement)
 MUTANTS = {
@@ -56,6 +59,13 @@ MUTANTS = {
     "mvs_f_function": ("mvs", "const double f = 1.0 - (a / r0) * (1.0 - c);",
                        "const double f = 1.0 - (a / r0) * (1.0 + c);"),
     "mvs_star_velocity_mass": ("mvs", "v[c] = Vc[c] - sp / m[0];", "v[c] = Vc[c] - sp / M;"),
+    # RKCK: a misread coupling coefficient, fifth- and fourth-order weights,
+    # stages that reuse the step's starting velocity, a loose acceptance test.
+    "rk_coupling_a52": ("rkck", "5.0 / 2.0", "2.0 / 5.0"),
+    "rk_weight_b6": ("rkck", "512.0 / 1771.0", "521.0 / 1771.0"),
+    "rk_weight_bs5": ("rkck", "277.0 / 14336.0", "227.0 / 14336.0"),
+    "rk_stage_velocity": ("rkck", "kx[s][k] = vs[k];", "kx[s][k] = v[k];"),
+    "rk_acceptance": ("rkck", "if (!(E <= 1.0)) {", "if (!(E <= 1e3)) {"),
 }
 
 
