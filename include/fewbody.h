@@ -174,6 +174,28 @@ fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
  * FB_SYS_UNBOUND. */
 fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *o);
 
+/* Runge-Kutta Cash-Karp integration (Sections 2.2.2 and 4.3.2): the embedded
+ * 4(5) pair of Cash & Karp (1990) on (x, v) with accelerations from Eq. 1,
+ * six acceleration evaluations per step or trial step, one body per lane,
+ * for systems of any supported size.  The step advances with the
+ * fifth-order weights; the error estimate is their difference from the
+ * fourth-order ones.
+ * fb_integrate_rkck_steps: exactly n_steps fixed steps of dt.
+ * fb_integrate_rkck: adaptive steps from each system's t to t_end, dt being
+ * the first trial step (> 0) and eps (> 0) the error tolerance.  With X and V
+ * the largest |x_i| and |v_i| of a system at the step's start, a trial is
+ * accepted when E = max_i max(|dx_i| / (eps X), |dv_i| / (eps V)) <= 1 (dx,
+ * dv the error estimate) and the next trial is h min(5, max(0.2,
+ * 0.9 E^(-1/5))); otherwise it is rejected (state and time unchanged) and
+ * retried with h max(0.1, 0.9 E^(-1/4)).  The last step is shortened onto
+ * t_end; a step below 1e-12 |t_end| stalls the system (FB_SYS_STALLED_DT).
+ * o: the quantum and max_steps; adaptive, stop_rules and compact must be 0
+ * and the schedule plain.  A later Hermite integration re-evaluates (a0,
+ * j0) first; fb_get_hermite_state does the same. */
+fb_status fb_integrate_rkck_steps(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *o);
+fb_status fb_integrate_rkck(fb_ensemble *e, double t_end, double dt, double eps,
+                            const fb_opts *o);
+
 /* Integrate every active system to t_end (Algorithm 1's destination time).
  * Fixed step (o->adaptive == 0): whole steps of dt, then one shortened step
  * that lands on t_end (skipped when the remainder is below 1e-9 |dt|); the

@@ -106,6 +106,10 @@ hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos
                          hipStream_t s);
 hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs_form,
                        hipStream_t s);
+// Runge-Kutta Cash-Karp (body per lane, any n): fixed steps (eps == 0) or
+// adaptive steps with error tolerance eps (P.adaptive nonzero).
+hipError_t launch_plain_rkck(const Bucket &B, int waves_per_group, const StepParams &P,
+                             double eps, hipStream_t s);
 // Mixed-variable symplectic integrator (n <= kMaxMvsBodies, system per
 // lane): conversion of a bucket to and from MVS form, fixed-step quanta, and
 // read-back of a bucket in MVS form as inertial positions and velocities.

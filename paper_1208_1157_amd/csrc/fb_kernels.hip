@@ -1169,6 +1169,13 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
         return;
     }
     B.t_end[s] = t_end;
+    if (adaptive == 3) {   // Runge-Kutta Cash-Karp: dt is the first trial step
+        B.nfull[s] = 0;
+        B.dt[s] = 0.0;
+        B.dtn[s] = dt;
+        B.status[s] = t < t_end ? ST_ACTIVE : ST_DONE;
+        return;
+    }
     if (adaptive) {
         B.nfull[s] = 0;
         B.dt[s] = 0.0;
@@ -1663,6 +1670,195 @@ __global__ __launch_bounds__(64) void k_unpack_mvs(Bucket B, const long long *__
         steps[o] = B.steps[s];
 }
 
+// ---------------------------------------------------------------------------
+// Runge-Kutta Cash-Karp 4(5), Sections 2.2.2 and 4.3.2 (body per lane)
+// ---------------------------------------------------------------------------
+// The embedded pair of Cash & Karp (ACM TOMS 16, 1990) on y = (x, v),
+// y' = (v, a(x)): six stages, each one acceleration evaluation (Eq. 1; a
+// lane holds one body and reads its partners' positions from the
+// wavefront's LDS slice, planets in ascending order, the star last).  The
+// step advances with the fifth-order weights; the error estimate is the
+// difference from the fourth-order weights.  Adaptive control: with X and V
+// the largest |x_i| and |v_i| of the system at the step's start,
+// E = max_i max(|dx_i| / (eps X), |dv_i| / (eps V)); E <= 1 accepts and
+// proposes h min(5, max(0.2, 0.9 E^(-1/5))) (a step shortened onto t_end
+// leaves the proposal as it was); E > 1 rejects (state and time unchanged)
+// and retries with h max(0.1, 0.9 E^(-1/4)).
+struct RkTableau {
+    // coupling coefficients a[stage][j], j < stage
+    static constexpr double a[6][5] = {
+        {0, 0, 0, 0, 0},
+        {1.0 / 5.0, 0, 0, 0, 0},
+        {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
+        {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
+        {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
+        {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+    // fifth-order weights, and fifth- minus fourth-order weights
+    static constexpr double b[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0,
+                                    512.0 / 1771.0};
+    static constexpr double e[6] = {37.0 / 378.0 - 2825.0 / 27648.0, 0.0,
+                                    250.0 / 621.0 - 18575.0 / 48384.0,
+                                    125.0 / 594.0 - 13525.0 / 55296.0, -277.0 / 14336.0,
+                                    512.0 / 1771.0 - 1.0 / 4.0};
+};
+
+// Acceleration of this lane's body (Eq. 1) from its partners' positions.
+template <int N>
+__device__ __forceinline__ void rk_accel(BplLds &L, const int lane, const int b, const int s,
+                                         const double (&xi)[3], double (&acc)[3])
+{
+    constexpr int S = 64 / N;
+    L.xy[lane] = make_double2(xi[0], xi[1]);
+    L.zvx[lane] = make_double2(xi[2], 0.0);
+    wave_sync();
+    acc[0] = acc[1] = acc[2] = 0.0;
+    const int skip = b == 0 ? (1 << 20) : b;
+#pragma unroll FB_BPL_UNROLL
+    for (int k = 0; k <= N - 2; ++k) {
+        // k < N-2: the other planets in ascending order; k = N-2: the star
+        // (for the star lane: the last planet)
+        const int j = k < N - 2 ? k + 1 + (k + 1 >= skip ? 1 : 0) : (b == 0 ? N - 1 : 0);
+        const int idx = j * S + s;
+        const double2 p0 = L.xy[idx];
+        const double2 p1 = L.zvx[idx];
+        const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
+        const double ri = rsqrt_nr(fma(rz, rz, fma(ry, ry, rx * rx)));
+        const double mr3 = L.m[idx] * (ri * ri * ri);
+        acc[0] = fma(mr3, rx, acc[0]);
+        acc[1] = fma(mr3, ry, acc[1]);
+        acc[2] = fma(mr3, rz, acc[2]);
+    }
+    wave_sync();
+}
+
+__device__ __forceinline__ double norm3d(const double (&p)[3])
+{
+    return sqrt(fma(p[2], p[2], fma(p[1], p[1], p[0] * p[0])));
+}
+
+// Six stages of (x, v) derivatives per lane do not fit the 4-waves budget
+// of the Hermite body-per-lane kernels without spilling; two waves per SIMD
+// give them registers.
+#ifndef FB_RK_WAVES
+#define FB_RK_WAVES 2
+#endif
+
+template <int N, bool ADV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FB_RK_WAVES)))
+void k_plain_rkck(Bucket B, StepParams P, double eps)
+{
+    constexpr int S = 64 / N;
+    using T = RkTableau;
+    const int wave = threadIdx.x >> 6;
+    const int tile = blockIdx.x * (blockDim.x >> 6) + wave;
+    const int first = tile * S;
+    if (first >= B.count)
+        return;
+    const int count = min(S, B.count - first);
+    BplLds &L = *reinterpret_cast<BplLds *>(wave_lds_base<sizeof(BplLds), false>());
+    const int lane = threadIdx.x & 63;
+    const int braw = lane / S;
+    const int b = braw < N ? braw : N - 1;
+    const int s = lane - braw * S;
+    const bool valid = braw < N && s < count;
+    const int slot = first + s;
+    const size_t pitch = B.pitch;
+    double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    Clock c;
+    c.status = ST_DONE;
+    if (valid) {
+        mi = B.st[(R_M * N + b) * pitch + slot];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            x[cc] = B.st[((R_X + cc) * N + b) * pitch + slot];
+            v[cc] = B.st[((R_V + cc) * N + b) * pitch + slot];
+        }
+        c = load_clock(B, slot);
+    }
+    L.m[lane] = mi;
+    wave_sync();
+    for (int q = 0; q < P.quantum; ++q) {
+        double h = 0.0;
+        bool last = false;
+        const bool act = valid && plan_step(c, P, h, last);
+        if (!__any(act))
+            break;
+        if (!act)
+            h = 0.0;
+        double kx[6][3], kv[6][3];
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            double xs[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                double dx = 0.0, dv = 0.0;
+#pragma unroll
+                for (int j = 0; j < st; ++j) {
+                    dx = fma(T::a[st][j], kx[j][cc], dx);
+                    dv = fma(T::a[st][j], kv[j][cc], dv);
+                }
+                xs[cc] = fma(h, dx, x[cc]);
+                kx[st][cc] = fma(h, dv, v[cc]);
+            }
+            rk_accel<N>(L, lane, b, s, xs, kv[st]);
+        }
+        double x5[3], v5[3], ex[3], ev[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            double sx = 0.0, sv = 0.0, ux = 0.0, uv = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                sx = fma(T::b[j], kx[j][cc], sx);
+                sv = fma(T::b[j], kv[j][cc], sv);
+                ux = fma(T::e[j], kx[j][cc], ux);
+                uv = fma(T::e[j], kv[j][cc], uv);
+            }
+            x5[cc] = fma(h, sx, x[cc]);
+            v5[cc] = fma(h, sv, v[cc]);
+            ex[cc] = h * ux;
+            ev[cc] = h * uv;
+        }
+        bool accept = true;
+        double dtp = 0.0;
+        if (ADV) {
+            const double X = sys_max<N>(L, lane, s, norm3d(x));
+            const double V = sys_max<N>(L, lane, s, norm3d(v));
+            const double E = sys_max<N>(L, lane, s,
+                                        fmax(norm3d(ex) / (eps * X), norm3d(ev) / (eps * V)));
+            accept = E <= 1.0;
+            if (act && !accept) {
+                if (!__builtin_isfinite(E))
+                    c.status = ST_NONFINITE;
+                else
+                    c.dtn = h * fmax(0.1, 0.9 * pow(E, -0.25));
+            }
+            dtp = last ? c.dtn : h * (E > 0.0 ? fmin(5.0, fmax(0.2, 0.9 * pow(E, -0.2))) : 5.0);
+        }
+        if (act && accept) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                x[cc] = x5[cc];
+                v[cc] = v5[cc];
+            }
+            finish_step(c, P, last, h, dtp);
+        }
+    }
+    if (!ADV) {
+        const int fl = sys_or<N>(L, lane, s, (finite3(x) && finite3(v)) ? 0 : 1);
+        if (valid && fl)
+            c.status = ST_NONFINITE;
+    }
+    if (valid) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            B.st[((R_X + cc) * N + b) * pitch + slot] = x[cc];
+            B.st[((R_V + cc) * N + b) * pitch + slot] = v[cc];
+        }
+        if (b == 0)
+            store_clock(B, slot, c);
+    }
+}
+
 // FP64 issue-ceiling probe for the roofline: each lane runs kFmaChains
 // independent FMA chains (a <- a*b + c, b slightly below 1 so values stay
 // bounded), so the rate is set by VALU issue rather than FMA latency.
@@ -1949,6 +2145,28 @@ hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s)
     if (B.count == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_count_active, grid_for(B.count, 256), dim3(256), 0, s, B, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_rkck(const Bucket &B, int waves_per_group, const StepParams &P,
+                             double eps, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+    const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
+    const int S = 64 / B.n;
+    const int tiles = (B.count + S - 1) / S;
+    const dim3 grid((unsigned)((tiles + W - 1) / W));
+    const size_t lds = sizeof(BplLds) * W;
+    if (eps > 0.0) {
+#define FB_L(NN) hipLaunchKernelGGL((k_plain_rkck<NN, true>), grid, dim3(64 * W), lds, s, B, P, eps)
+        FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    } else {
+#define FB_L(NN) hipLaunchKernelGGL((k_plain_rkck<NN, false>), grid, dim3(64 * W), lds, s, B, P, eps)
+        FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
+    }
     return hipGetLastError();
 }
 

@@ -247,7 +247,10 @@ struct fb_ensemble {
     int *d_mapping = nullptr;
     int *h_pinned = nullptr;        // pinned host ints for control reads
     hipStream_t capture_stream = nullptr;
-    bool mvs_form = false;          // state rows hold the MVS variables, not (x, v, a0, j0)
+    // What the state rows hold: (x, v, a0, j0) ready for Hermite; the MVS
+    // variables; or (x, v) with (a0, j0) stale after a Runge-Kutta run.
+    enum Form { FORM_HERMITE, FORM_MVS, FORM_XV } form = FORM_HERMITE;
+    bool mvs_form() const { return form == FORM_MVS; }
 };
 
 namespace {
@@ -576,14 +579,63 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
 // set-up evaluation of (a0, j0).
 fb_status ensure_inertial(fb_ensemble *e)
 {
-    if (!e->mvs_form)
+    if (e->form == fb_ensemble::FORM_HERMITE)
         return FB_OK;
     for (const Bucket &B : e->buckets) {
-        FB_HIP(launch_mvs_leave(B, e->stream));
+        if (e->form == fb_ensemble::FORM_MVS)
+            FB_HIP(launch_mvs_leave(B, e->stream));
         FB_HIP(launch_prepare(B, e->stream));
     }
-    e->mvs_form = false;
+    e->form = fb_ensemble::FORM_HERMITE;
     return FB_OK;
+}
+
+// (x, v) in the rows, for integrators that carry nothing else.
+fb_status ensure_xv(fb_ensemble *e)
+{
+    if (e->form == fb_ensemble::FORM_MVS) {
+        for (const Bucket &B : e->buckets)
+            FB_HIP(launch_mvs_leave(B, e->stream));
+        e->form = fb_ensemble::FORM_XV;
+    }
+    return FB_OK;
+}
+
+// Runge-Kutta quanta: one body-per-lane launch per bucket and quantum.
+fb_status run_rkck(fb_ensemble *e, const fb_opts &o, int adaptive, double eps,
+                   long long step_bound)
+{
+    const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
+    for (;;) {
+        for (const Bucket &B : e->buckets) {
+            StepParams P = make_params(o, quantum);
+            P.adaptive = adaptive;
+            ProfScope ps(e->stream);
+            FB_HIP(launch_plain_rkck(B, 2, P, eps, e->stream));
+        }
+        if (quantum == INT_MAX)
+            return FB_OK;
+        if (step_bound >= 0) {
+            step_bound -= quantum;
+            if (step_bound <= 0)
+                return FB_OK;
+            continue;
+        }
+        int act = 0;
+        fb_status st = count_active(e, act);
+        if (st != FB_OK)
+            return st;
+        if (act == 0)
+            return FB_OK;
+    }
+}
+
+fb_status check_rk_opts(const fb_opts &o)
+{
+    if (o.adaptive || o.stop_rules || o.compact || o.schedule != FB_SCHED_PLAIN)
+        return fail(FB_E_INVAL, "Runge-Kutta takes the plain schedule without stop rules "
+                                "(opts.adaptive, stop_rules and compact must be 0, schedule plain)");
+    return check_opts(o);
 }
 
 // MVS quanta: one system-per-lane launch per bucket and quantum.
@@ -789,14 +841,69 @@ fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_
                         kMaxMvsBodies, B.n);
     if (n_steps == 0 || e->n_sys == 0)
         return FB_OK;
-    if (!e->mvs_form) {
+    if (!e->mvs_form()) {
         for (const Bucket &B : e->buckets)
             FB_HIP(launch_mvs_enter(B, e->stream));
-        e->mvs_form = true;
+        e->form = fb_ensemble::FORM_MVS;
     }
     for (const Bucket &B : e->buckets)
         FB_HIP(launch_begin_run(B, 1, n_steps, 0.0, dt, 0, 0.0, e->stream));
     return run_mvs(e, o, n_steps);
+}
+
+fb_status fb_integrate_rkck_steps(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *po)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    fb_status st = check_rk_opts(o);
+    if (st != FB_OK)
+        return st;
+    if (n_steps < 0)
+        return fail(FB_E_INVAL, "n_steps must be >= 0");
+    if (!(std::isfinite(dt) && dt != 0.0))
+        return fail(FB_E_INVAL, "dt must be finite and non-zero");
+    if (n_steps == 0 || e->n_sys == 0)
+        return FB_OK;
+    st = ensure_xv(e);
+    if (st != FB_OK)
+        return st;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_begin_run(B, 1, n_steps, 0.0, dt, 0, 0.0, e->stream));
+    e->form = fb_ensemble::FORM_XV;
+    return run_rkck(e, o, 0, 0.0, n_steps);
+}
+
+fb_status fb_integrate_rkck(fb_ensemble *e, double t_end, double dt, double eps,
+                            const fb_opts *po)
+{
+    if (!e)
+        return fail(FB_E_INVAL, "ensemble is NULL");
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    fb_status st = check_rk_opts(o);
+    if (st != FB_OK)
+        return st;
+    if (!std::isfinite(t_end))
+        return fail(FB_E_INVAL, "t_end must be finite");
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(FB_E_INVAL, "dt (the first trial step) must be finite and > 0");
+    if (!(std::isfinite(eps) && eps > 0.0))
+        return fail(FB_E_INVAL, "eps must be finite and > 0");
+    if (e->n_sys == 0)
+        return FB_OK;
+    st = ensure_xv(e);
+    if (st != FB_OK)
+        return st;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_begin_run(B, 0, 0, t_end, dt, 3, 0.0, e->stream));
+    e->form = fb_ensemble::FORM_XV;
+    return run_rkck(e, o, 3, eps, -1);
 }
 
 fb_status fb_integrate(fb_ensemble *e, double t_end, double dt, const fb_opts *po)
@@ -845,7 +952,7 @@ fb_status fb_get_state(fb_ensemble *e, double *pos, double *vel, double *t, int3
     long long *d_steps = (long long *)(d_t + ns);
     int *d_status = (int *)(d_steps + ns);
     for (const Bucket &B : e->buckets) {
-        if (e->mvs_form)
+        if (e->mvs_form())
             FB_HIP(launch_unpack_mvs(B, e->d_orig_off, pos ? d_pos : nullptr, vel ? d_vel : nullptr,
                                      t ? d_t : nullptr, status ? d_status : nullptr,
                                      steps ? d_steps : nullptr, e->stream));
@@ -872,9 +979,14 @@ fb_status fb_get_hermite_state(fb_ensemble *e, double *acc0, double *jerk0, doub
 {
     if (!e)
         return fail(FB_E_INVAL, "ensemble is NULL");
-    if (e->mvs_form)
+    if (e->mvs_form())
         return fail(FB_E_STATE, "the ensemble holds MVS state; a Hermite integration restores "
                                 "(a0, j0)");
+    if (e->form == fb_ensemble::FORM_XV) {   // re-evaluate the stale (a0, j0)
+        fb_status st = ensure_inertial(e);
+        if (st != FB_OK)
+            return st;
+    }
     const size_t N = (size_t)e->L.n_bodies, ns = (size_t)e->n_sys;
     if (ns == 0)
         return FB_OK;
@@ -902,7 +1014,7 @@ fb_status fb_diagnostics(fb_ensemble *e, double *energy, double *angmom)
         return FB_OK;
     double *d_E = e->d_diag, *d_L = d_E + ns;
     for (const Bucket &B : e->buckets)
-        FB_HIP(launch_diag(B, d_E, d_L, e->mvs_form, e->stream));
+        FB_HIP(launch_diag(B, d_E, d_L, e->mvs_form(), e->stream));
     if (energy)
         FB_HIP(hipMemcpyAsync(energy, d_E, 8 * ns, hipMemcpyDeviceToHost, e->stream));
     if (angmom)

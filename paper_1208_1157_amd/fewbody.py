@@ -79,6 +79,8 @@ _SIGS = {
                                                  ctypes.POINTER(_p)]),
     "fb_integrate_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate_mvs": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
+    "fb_integrate_rkck_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
+    "fb_integrate_rkck": (ctypes.c_int, [_p, _d, _d, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate": (ctypes.c_int, [_p, _d, _d, ctypes.POINTER(FbOpts)]),
     "fb_synchronize": (ctypes.c_int, [_p]),
     "fb_get_state": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
@@ -256,6 +258,17 @@ class Ensemble:
         (fb_integrate_mvs; systems of at most MAX_MVS_BODIES bodies)."""
         o = (opts or Opts()).c()
         _check(_lib.fb_integrate_mvs(self._handle, int(n_steps), float(dt), ctypes.byref(o)))
+
+    def integrate_rkck_steps(self, n_steps, dt, opts: Opts | None = None):
+        """n_steps fixed Runge-Kutta Cash-Karp steps (fb_integrate_rkck_steps)."""
+        o = (opts or Opts()).c()
+        _check(_lib.fb_integrate_rkck_steps(self._handle, int(n_steps), float(dt), ctypes.byref(o)))
+
+    def integrate_rkck(self, t_end, dt, eps, opts: Opts | None = None):
+        """Adaptive Runge-Kutta Cash-Karp to t_end, first trial step dt,
+        tolerance eps (fb_integrate_rkck)."""
+        o = (opts or Opts()).c()
+        _check(_lib.fb_integrate_rkck(self._handle, float(t_end), float(dt), float(eps), ctypes.byref(o)))
 
     def integrate(self, t_end, dt=0.0, opts: Opts | None = None):
         o = (opts or Opts()).c()
