@@ -23,8 +23,9 @@ Printed as one JSON line, with
                 uneven lifetimes 65536 x (4..8) with adaptive steps and stop
                 rules on a bounded horizon, plain launches vs persistent
                 quanta with compaction; Section 5.1's initial conditions at
-                Table 3's size, beside the paper's times; the MVS integrator
-                on the headline ensemble and the Section 5.1 systems.
+                Table 3's size, beside the paper's times; the MVS and
+                Runge-Kutta Cash-Karp integrators on the headline ensemble,
+                the ragged workload and the Section 5.1 systems.
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 # FETCH_SIZE / WRITE_SIZE counter passes (scaled by a 256 MiB copy kernel's
 # reading) recorded in profiles/, keyed by the kernel source they measured.
 MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1,
-                    "1c9dff3d544099cf": 92417308.4}
+                    "1c9dff3d544099cf": 92417308.4, "234f298587126ea3": 92405022.4}
 # Hardware counters of the same kernel on this workload (profiles/), keyed the
 # same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
 # lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
@@ -53,6 +54,8 @@ MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596
 MEASURED_COUNTERS = {
     "1c9dff3d544099cf": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9671,
                          "shader_clock_ghz": 2.018, "valu_insts_per_system_step": 388.01},
+    "234f298587126ea3": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9753,
+                         "shader_clock_ghz": 1.996, "valu_insts_per_system_step": 388.01},
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
@@ -88,7 +91,7 @@ def host_threads() -> int:
     return max(1, min(16, c))
 
 
-def cpu_baseline(ens, h, target_s=15.0):
+def cpu_baseline(ens, h, target_s=20.0):
     """The oracle (plain FP64 C, one system per thread) on this host's cores,
     on all systems of the ensemble for a bounded number of steps."""
     import oracle
@@ -230,6 +233,32 @@ def mvs_extras(fb, gen, torch, log, dt=1e-2, steps=20000):
         assert (st["status"] == fb.DONE).all()
         rows.append({"n": n, "seconds": t, "system_steps_per_s": e.n_sys * n_steps / t})
     out["paper_ics_one_time_unit"] = rows
+    return out
+
+
+def rkck_extras(fb, gen, torch, log, steps=2000):
+    """The Runge-Kutta Cash-Karp integrator (Sections 2.2.2 and 4.3.2): fixed
+    steps on the headline ensemble (dt 2pi/1000) and on the ragged workload
+    (dt 2pi/2000), and adaptive steps (eps 1e-10, one inner orbit) on
+    Section 5.1's three-body systems.  Work unit: system-steps (six
+    acceleration evaluations each); adaptive counts accepted steps."""
+    out = {}
+    ens, _ = gen.workload("homog_131072x3")
+    t, st = timed(fb, torch, ens, lambda E: E.integrate_rkck_steps(steps, 2 * math.pi / 1000))
+    assert (st["status"] == fb.DONE).all()
+    out["homog_131072x3_fixed"] = {"steps": steps, "seconds": t, "system_steps_per_s": ens.n_sys * steps / t}
+    log(f"[bench] RKCK homog_131072x3: {ens.n_sys * steps / t:.3e} system-steps/s")
+    rg, p = gen.workload("ragged_65536x3-15")
+    t, st = timed(fb, torch, rg, lambda E: E.integrate_rkck_steps(steps, p["dt"]))
+    assert (st["status"] == fb.DONE).all()
+    out["ragged_65536x3-15_fixed"] = {"steps": steps, "seconds": t, "system_steps_per_s": rg.n_sys * steps / t}
+    pi3 = gen.paper_ics(131072, 3)
+    t, st = timed(fb, torch, pi3, lambda E: E.integrate_rkck(2 * math.pi, 0.01, 1e-10))
+    assert (st["status"] == fb.DONE).all()
+    acc = float(st["steps"].sum())
+    out["paper_ics_n3_adaptive"] = {"eps": 1e-10, "t_end": 2 * math.pi, "seconds": t,
+                                    "accepted_steps_per_system": acc / pi3.n_sys,
+                                    "system_steps_per_s": acc / t}
     return out
 
 
@@ -404,6 +433,7 @@ def main():
         restore_plans()
         extras["paper_ics"] = paper_ic_extras(fb, gen, torch, log)
         extras["mvs"] = mvs_extras(fb, gen, torch, log)
+        extras["rkck"] = rkck_extras(fb, gen, torch, log)
     if extras:
         result["extras"] = extras
     if not args.no_cpu:
