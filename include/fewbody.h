@@ -174,6 +174,44 @@ fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
  * FB_SYS_UNBOUND. */
 fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *o);
 
+/* ------------------------------------------------- monitors and logging */
+/* A monitor that logs every system's state at regular steps into a device
+ * buffer (the logging of the generic integrator, Section 4.3), optionally
+ * reduced on the device before anything crosses to the host (Section 4.4's
+ * data reduction: the star's radial velocity only, or energy and angular
+ * momentum). */
+enum { FB_LOG_STATE = 0, FB_LOG_RV = 1, FB_LOG_ENERGY = 2 };
+
+typedef struct {
+    int32_t kind;          /* FB_LOG_*                                               */
+    int32_t every;         /* a record after every `every` steps (>= 1)              */
+    int32_t max_records;   /* records per system the buffer holds                    */
+    int32_t reserved;      /* 0                                                      */
+    double los[3];         /* FB_LOG_RV: line of sight (any non-zero length)         */
+    void *d_buffer;        /* DEVICE memory, caller-owned, fb_log_bytes(...) bytes   */
+    size_t buffer_bytes;
+} fb_log_spec;
+
+/* Bytes of a log buffer for systems of these body counts (caller's order)
+ * and max_records records each; 0 on invalid input.  Layouts (doubles,
+ * system index o in the caller's order, record k):
+ *   FB_LOG_STATE:  system o's block starts at max_records * (o + 6 off[o])
+ *                  with off the body offsets; record k holds t, then
+ *                  pos [n_o][3], then vel [n_o][3];
+ *   FB_LOG_RV:     [o][k][2] = t, (v_star - v_cm) . los / |los|;
+ *   FB_LOG_ENERGY: [o][k][5] = t, E (Eq. 6), L[3]. */
+size_t fb_log_bytes(int32_t n_sys, const int32_t *n_body, int32_t kind, int32_t max_records);
+
+/* fb_integrate_steps (fixed steps, plain schedule) with the monitor of `log`:
+ * record 0 is the state before the first step, then one record after every
+ * `every` steps and one at the end; the integration itself is identical to
+ * the unlogged call.  *n_records (may be NULL) gets the records written.
+ * FB_E_INVAL if the buffer is too small or holds fewer than the run's
+ * records, or for the persistent schedule. */
+fb_status fb_integrate_steps_logged(fb_ensemble *e, int64_t n_steps, double dt,
+                                    const fb_opts *o, const fb_log_spec *log,
+                                    int32_t *n_records);
+
 /* Runge-Kutta Cash-Karp integration (Sections 2.2.2 and 4.3.2): the embedded
  * 4(5) pair of Cash & Karp (1990) on (x, v) with accelerations from Eq. 1,
  * six acceleration evaluations per step or trial step, one body per lane,

@@ -106,6 +106,11 @@ hipError_t launch_unpack(const Bucket &B, const long long *orig_off, double *pos
                          hipStream_t s);
 hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs_form,
                        hipStream_t s);
+// Monitor record k of every system of B (kind 0 state, 1 star RV along the
+// unit vector los, 2 energy and angular momentum) into a log buffer whose
+// layout fb_log_bytes describes.
+hipError_t launch_log(const Bucket &B, const long long *orig_off, int kind, const double *los,
+                      int k, int max_records, double *out, hipStream_t s);
 // Runge-Kutta Cash-Karp (body per lane, any n): fixed steps (eps == 0) or
 // adaptive steps with error tolerance eps (P.adaptive nonzero).
 hipError_t launch_plain_rkck(const Bucket &B, int waves_per_group, const StepParams &P,

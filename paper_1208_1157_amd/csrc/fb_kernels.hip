@@ -1242,18 +1242,13 @@ __global__ void k_unpack(Bucket B, const long long *__restrict__ orig_off, doubl
 template <int N>
 __device__ __forceinline__ void from_mvs(const double (&m)[N], double (&x)[N][3], double (&v)[N][3]);
 
-// Energy (each pair once) and angular momentum about the origin, of a bucket
-// in inertial form or (MVS) in MVS form, converted first.
-template <int N, bool MVS>
-__global__ void k_diag(Bucket B, double *energy, double *angmom)
+// Energy (Eq. 6, each pair once) and angular momentum about the origin of
+// one system.
+template <int N>
+__device__ __forceinline__ void sys_energy(const double (&m)[N], const double (&x)[N][3],
+                                          const double (&v)[N][3], double &energy,
+                                          double (&L)[3])
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= B.count)
-        return;
-    double m[N], x[N][3], v[N][3];
-    load_xv<N>(B, s, m, x, v);
-    if (MVS)
-        from_mvs<N>(m, x, v);
     double kin = 0.0, pot = 0.0, L0 = 0.0, L1 = 0.0, L2 = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -1269,13 +1264,87 @@ __global__ void k_diag(Bucket B, double *energy, double *angmom)
             const double dx = x[i][0] - x[j][0], dy = x[i][1] - x[j][1], dz = x[i][2] - x[j][2];
             pot += m[i] * m[j] / sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
         }
+    energy = kin - pot;
+    L[0] = L0;
+    L[1] = L1;
+    L[2] = L2;
+}
+
+// Energy and angular momentum of every system of a bucket in inertial form
+// or (MVS) in MVS form, converted first.
+template <int N, bool MVS>
+__global__ void k_diag(Bucket B, double *energy, double *angmom)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3];
+    load_xv<N>(B, s, m, x, v);
+    if (MVS)
+        from_mvs<N>(m, x, v);
+    double E, L[3];
+    sys_energy<N>(m, x, v, E, L);
     const int o = B.orig[s];
     if (energy)
-        energy[o] = kin - pot;
+        energy[o] = E;
     if (angmom) {
-        angmom[3 * o + 0] = L0;
-        angmom[3 * o + 1] = L1;
-        angmom[3 * o + 2] = L2;
+        angmom[3 * o + 0] = L[0];
+        angmom[3 * o + 1] = L[1];
+        angmom[3 * o + 2] = L[2];
+    }
+}
+
+// Monitor record k of every system of a bucket (Section 4.3's logging, with
+// Section 4.4's data reduction), into the caller's log buffer:
+//   kind 0 (state):  system o's block starts at max_records (o + 6 off[o])
+//                    doubles; record k holds t, then pos [n][3], vel [n][3];
+//   kind 1 (RV):     [o][k][2] = t and the star's velocity relative to the
+//                    system's centre of mass along the unit line of sight l;
+//   kind 2 (energy): [o][k][5] = t, E, L.
+template <int N>
+__global__ void k_log(Bucket B, const long long *__restrict__ orig_off, int kind, double lx,
+                      double ly, double lz, int k, int max_records, double *out)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    double m[N], x[N][3], v[N][3];
+    load_xv<N>(B, s, m, x, v);
+    const int o = B.orig[s];
+    const double t = B.t[s];
+    if (kind == 1) {
+        double M = 0.0, p0 = 0.0, p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            M += m[i];
+            p0 = fma(m[i], v[i][0], p0);
+            p1 = fma(m[i], v[i][1], p1);
+            p2 = fma(m[i], v[i][2], p2);
+        }
+        const double rv = fma(v[0][2] - p2 / M, lz, fma(v[0][1] - p1 / M, ly, (v[0][0] - p0 / M) * lx));
+        double *r = out + ((size_t)o * max_records + k) * 2;
+        r[0] = t;
+        r[1] = rv;
+    } else if (kind == 2) {
+        double E, L[3];
+        sys_energy<N>(m, x, v, E, L);
+        double *r = out + ((size_t)o * max_records + k) * 5;
+        r[0] = t;
+        r[1] = E;
+        r[2] = L[0];
+        r[3] = L[1];
+        r[4] = L[2];
+    } else {
+        double *r = out + (size_t)max_records * ((size_t)o + 6 * (size_t)orig_off[o]) +
+                    (size_t)k * (1 + 6 * N);
+        r[0] = t;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                r[1 + 3 * b + c] = x[b][c];
+                r[1 + 3 * N + 3 * b + c] = v[b][c];
+            }
     }
 }
 
@@ -2145,6 +2214,18 @@ hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s)
     if (B.count == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_count_active, grid_for(B.count, 256), dim3(256), 0, s, B, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_log(const Bucket &B, const long long *orig_off, int kind, const double *los,
+                      int k, int max_records, double *out, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+#define FB_L(NN) hipLaunchKernelGGL(k_log<NN>, grid_for(B.count, 64), dim3(64), 0, s, B, orig_off, \
+                                    kind, los[0], los[1], los[2], k, max_records, out)
+    FB_SWITCH_N(B.n, FB_L)
+#undef FB_L
     return hipGetLastError();
 }
 

@@ -851,6 +851,96 @@ fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_
     return run_mvs(e, o, n_steps);
 }
 
+size_t fb_log_bytes(int32_t n_sys, const int32_t *n_body, int32_t kind, int32_t max_records)
+{
+    if (n_sys < 0 || (n_sys > 0 && !n_body) || max_records < 1)
+        return 0;
+    size_t bodies = 0;
+    for (int32_t s = 0; s < n_sys; ++s) {
+        if (n_body[s] < 2 || n_body[s] > kMaxBodies)
+            return 0;
+        bodies += (size_t)n_body[s];
+    }
+    const size_t R = (size_t)max_records;
+    switch (kind) {
+    case FB_LOG_STATE: return 8 * R * ((size_t)n_sys + 6 * bodies);
+    case FB_LOG_RV: return 8 * R * 2 * (size_t)n_sys;
+    case FB_LOG_ENERGY: return 8 * R * 5 * (size_t)n_sys;
+    default: return 0;
+    }
+}
+
+fb_status fb_integrate_steps_logged(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *po,
+                                    const fb_log_spec *log, int32_t *n_records)
+{
+    if (!e || !log)
+        return fail(FB_E_INVAL, "ensemble and log are required");
+    if (n_records)
+        *n_records = 0;
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    if (o.adaptive)
+        return fail(FB_E_INVAL, "logged integration takes fixed steps (opts.adaptive must be 0)");
+    if (o.schedule != FB_SCHED_PLAIN)
+        return fail(FB_E_INVAL, "logged integration runs the plain schedule");
+    fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    if (n_steps < 0 || !(std::isfinite(dt) && dt != 0.0))
+        return fail(FB_E_INVAL, "n_steps must be >= 0 and dt finite and non-zero");
+    if (log->every < 1 || log->max_records < 1)
+        return fail(FB_E_INVAL, "log.every and log.max_records must be >= 1");
+    const long long records = 1 + n_steps / log->every + (n_steps % log->every ? 1 : 0);
+    if (records > log->max_records)
+        return fail(FB_E_INVAL, "the run makes %lld records, log.max_records is %d", records,
+                    log->max_records);
+    const size_t need = fb_log_bytes(e->n_sys, e->n_body.data(), log->kind, log->max_records);
+    if (need == 0 && e->n_sys > 0)
+        return fail(FB_E_INVAL, "unknown log kind %d", log->kind);
+    if (!log->d_buffer || log->buffer_bytes < need)
+        return fail(FB_E_INVAL, "log buffer of %zu bytes, %zu needed", log->buffer_bytes, need);
+    double los[3] = {0.0, 0.0, 1.0};
+    if (log->kind == FB_LOG_RV) {
+        const double l2 = log->los[0] * log->los[0] + log->los[1] * log->los[1] +
+                          log->los[2] * log->los[2];
+        if (!(std::isfinite(l2) && l2 > 0.0))
+            return fail(FB_E_INVAL, "log.los must be a finite non-zero vector");
+        const double inv = 1.0 / std::sqrt(l2);
+        for (int c = 0; c < 3; ++c)
+            los[c] = log->los[c] * inv;
+    }
+    if (e->n_sys == 0)
+        return FB_OK;
+    st = ensure_inertial(e);
+    if (st != FB_OK)
+        return st;
+    double *out = static_cast<double *>(log->d_buffer);
+    int k = 0;
+    for (const Bucket &B : e->buckets)
+        FB_HIP(launch_log(B, e->d_orig_off, log->kind, los, k, log->max_records, out, e->stream));
+    ++k;
+    if (n_steps > 0) {
+        for (const Bucket &B : e->buckets)
+            FB_HIP(launch_begin_run(B, 1, n_steps, 0.0, dt, 0, 0.0, e->stream));
+        fb_opts oq = o;
+        oq.steps_per_quantum = log->every;
+        for (long long done = 0; done < n_steps; done += log->every) {
+            st = run_plain(e, oq, log->every);
+            if (st != FB_OK)
+                return st;
+            for (const Bucket &B : e->buckets)
+                FB_HIP(launch_log(B, e->d_orig_off, log->kind, los, k, log->max_records, out,
+                                  e->stream));
+            ++k;
+        }
+    }
+    if (n_records)
+        *n_records = k;
+    return FB_OK;
+}
+
 fb_status fb_integrate_rkck_steps(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *po)
 {
     if (!e)

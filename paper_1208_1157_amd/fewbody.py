@@ -60,6 +60,12 @@ class FbServerStats(ctypes.Structure):
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
 
+class FbLogSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("every", ctypes.c_int32), ("max_records", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("los", ctypes.c_double * 3), ("d_buffer", ctypes.c_void_p),
+                ("buffer_bytes", ctypes.c_size_t)]
+
+
 class FbTuneEntry(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("mapping", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
                 ("groups_per_cu", ctypes.c_int32), ("ms", ctypes.c_double), ("chosen", ctypes.c_int32),
@@ -68,6 +74,7 @@ class FbTuneEntry(ctypes.Structure):
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = range(5)
 POLICY_FAIR, POLICY_SRPT = 0, 1
+LOG_STATE, LOG_RV, LOG_ENERGY = 0, 1, 2
 
 _p = ctypes.c_void_p
 _i32, _i64, _d, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -79,6 +86,9 @@ _SIGS = {
                                                  ctypes.POINTER(_p)]),
     "fb_integrate_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate_mvs": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
+    "fb_log_bytes": (_sz, [_i32, _p, _i32, _i32]),
+    "fb_integrate_steps_logged": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts),
+                                                 ctypes.POINTER(FbLogSpec), _p]),
     "fb_integrate_rkck_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate_rkck": (ctypes.c_int, [_p, _d, _d, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate": (ctypes.c_int, [_p, _d, _d, ctypes.POINTER(FbOpts)]),
@@ -252,6 +262,52 @@ class Ensemble:
     def integrate_steps(self, n_steps, dt, opts: Opts | None = None):
         o = (opts or Opts()).c()
         _check(_lib.fb_integrate_steps(self._handle, int(n_steps), float(dt), ctypes.byref(o)))
+
+    def integrate_steps_logged(self, n_steps, dt, every, kind=LOG_RV, los=(0.0, 0.0, 1.0),
+                               opts: Opts | None = None, max_records=None):
+        """fb_integrate_steps with a monitor that logs every `every` steps
+        into a device buffer (torch-owned); returns the records on the host:
+        LOG_RV -> (t, rv) [n_sys, R] each; LOG_ENERGY -> (t, E, L)
+        [n_sys, R], [n_sys, R], [n_sys, R, 3]; LOG_STATE -> (t [n_sys, R],
+        pos [R, N, 3], vel [R, N, 3])."""
+        if every < 1:
+            raise FewbodyError(E_INVAL, "every must be >= 1")
+        R = max_records or (1 + n_steps // every + (1 if n_steps % every else 0))
+        torch = self._torch
+        nb = self.n_body
+        nbytes = int(_lib.fb_log_bytes(int(nb.shape[0]), _ptr(nb), int(kind), int(R)))
+        if nbytes == 0:
+            raise FewbodyError(E_INVAL, "invalid log kind or record count")
+        with torch.cuda.stream(self.stream):
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+        spec = FbLogSpec(int(kind), int(every), int(R), 0, (ctypes.c_double * 3)(*los),
+                         ctypes.c_void_p(buf.data_ptr()), nbytes)
+        o = (opts or Opts()).c()
+        n_rec = ctypes.c_int32()
+        _check(_lib.fb_integrate_steps_logged(self._handle, int(n_steps), float(dt), ctypes.byref(o),
+                                              ctypes.byref(spec), ctypes.byref(n_rec)))
+        self.synchronize()
+        host = buf.cpu().numpy().view(np.float64)
+        k, S = n_rec.value, int(nb.shape[0])
+        if kind == LOG_RV:
+            a = host.reshape(S, R, 2)[:, :k]
+            return a[..., 0], a[..., 1]
+        if kind == LOG_ENERGY:
+            a = host.reshape(S, R, 5)[:, :k]
+            return a[..., 0], a[..., 1], a[..., 2:5]
+        off = np.concatenate([[0], np.cumsum(nb)])
+        N = int(off[-1])
+        t = np.empty((S, k))
+        pos = np.empty((k, N, 3))
+        vel = np.empty((k, N, 3))
+        for o_ in range(S):
+            n = int(nb[o_])
+            base = R * (o_ + 6 * int(off[o_]))
+            blk = host[base:base + R * (1 + 6 * n)].reshape(R, 1 + 6 * n)[:k]
+            t[o_] = blk[:, 0]
+            pos[:, off[o_]:off[o_ + 1]] = blk[:, 1:1 + 3 * n].reshape(k, n, 3)
+            vel[:, off[o_]:off[o_ + 1]] = blk[:, 1 + 3 * n:].reshape(k, n, 3)
+        return t, pos, vel
 
     def integrate_mvs(self, n_steps, dt, opts: Opts | None = None):
         """n_steps fixed steps of the mixed-variable symplectic integrator
@@ -427,3 +483,8 @@ class Server:
 def from_gen(ens, **kw) -> Ensemble:
     """Ensemble from a paper_1208_1157_amd.gen.Ensemble."""
     return Ensemble(ens.n_body, ens.mass, ens.pos, ens.vel, **kw)
+
+
+def log_bytes(n_body, kind, max_records) -> int:
+    nb = np.ascontiguousarray(n_body, dtype=np.int32)
+    return int(_lib.fb_log_bytes(int(nb.shape[0]), _ptr(nb), int(kind), int(max_records)))

@@ -135,3 +135,24 @@ def test_server_request_bytes(fbmod):
 
 def test_fma_ceiling_rejects_null(fbmod):
     assert fbmod.lib().fb_fp64_fma_ceiling(None) == fbmod.E_INVAL
+
+
+def test_log_bytes(fbmod):
+    """Log buffer sizes follow the documented layouts; invalid kinds, record
+    counts and body counts give 0."""
+    nb = [3, 5, 2]
+    R = 7
+    assert fbmod.log_bytes(nb, fbmod.LOG_RV, R) == 8 * R * 2 * 3
+    assert fbmod.log_bytes(nb, fbmod.LOG_ENERGY, R) == 8 * R * 5 * 3
+    assert fbmod.log_bytes(nb, fbmod.LOG_STATE, R) == 8 * R * sum(1 + 6 * n for n in nb)
+    assert fbmod.log_bytes(nb, 3, R) == 0
+    assert fbmod.log_bytes(nb, fbmod.LOG_RV, 0) == 0
+    assert fbmod.log_bytes([3, 17], fbmod.LOG_RV, R) == 0
+    assert fbmod.log_bytes([], fbmod.LOG_STATE, R) == 0
+
+
+def test_logged_integration_rejects_null(fbmod):
+    L = fbmod.lib()
+    spec = fbmod.FbLogSpec()
+    assert L.fb_integrate_steps_logged(None, 10, 0.01, None, ctypes.byref(spec), None) == fbmod.E_INVAL
+    assert ctypes.sizeof(fbmod.FbLogSpec) == 56

@@ -1,0 +1,157 @@
+"""The monitor and its log buffer (Section 4.3) with Section 4.4's data
+reduction, against the Hermite oracle: logged states, the star's radial
+velocity and the conserved quantities at every record; the logged run ends
+bitwise where the unlogged one does; argument checks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_1157_amd import gen
+from tests.helpers import REL_TOL, per_system_rel_err, threads
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2 * math.pi
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def ragged():
+    parts = [gen.ragged_hill(150, seed=61, n_lo=2, n_hi=16), gen.paper_ics(4, 3), gen.paper_ics(4, 6)]
+    nb = np.concatenate([p.n_body for p in parts])
+    return gen.Ensemble(nb, np.concatenate([p.mass for p in parts]), np.concatenate([p.pos for p in parts]),
+                        np.concatenate([p.vel for p in parts]))
+
+
+def oracle_records(ora, ens, dt, n_steps, every):
+    """Oracle states at every record: step counts 0, every, 2 every, ...,
+    n_steps, each integrated from the initial state."""
+    ks = sorted(set(list(range(0, n_steps, every)) + [n_steps]))
+    out = []
+    for k in ks:
+        if k == 0:
+            out.append((ens.pos.copy(), ens.vel.copy()))
+        else:
+            x, v, _, _ = ora.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, dt, k,
+                                            nthreads=threads())
+            out.append((x, v))
+    return ks, out
+
+
+def star_rv(ens, vel, los):
+    """The star's velocity relative to the system's centre of mass, along
+    the unit line of sight."""
+    l = np.asarray(los, float) / np.linalg.norm(los)
+    off = ens.offsets
+    rv = np.empty(ens.n_sys)
+    for s in range(ens.n_sys):
+        m, v = ens.mass[off[s]:off[s + 1]], vel[off[s]:off[s + 1]]
+        rv[s] = (v[0] - m @ v / m.sum()) @ l
+    return rv
+
+
+def vel_scale(ens, vel):
+    off = ens.offsets
+    return np.array([np.linalg.norm(vel[off[s]:off[s + 1]], axis=1).max() for s in range(ens.n_sys)])
+
+
+def test_state_records_match_the_oracle(fb, ora):
+    ens = ragged()
+    dt, n_steps, every = TWO_PI / 400, 250, 60        # records at 0, 60, ..., 240, 250
+    say("log state", ens.n_sys)
+    E = fb.from_gen(ens)
+    t, pos, vel = E.integrate_steps_logged(n_steps, dt, every, kind=fb.LOG_STATE)
+    E.close()
+    ks, ref = oracle_records(ora, ens, dt, n_steps, every)
+    assert t.shape == (ens.n_sys, len(ks)) and pos.shape[0] == len(ks)
+    assert np.array_equal(pos[0], ens.pos) and np.array_equal(vel[0], ens.vel)
+    for r, (k, (x, v)) in enumerate(zip(ks, ref)):
+        assert np.allclose(t[:, r], k * dt, rtol=1e-13, atol=0), r
+        ex = per_system_rel_err(ens.n_body, pos[r], x)
+        ev = per_system_rel_err(ens.n_body, vel[r], v)
+        assert ex.max() <= REL_TOL and ev.max() <= REL_TOL, (r, ex.max(), ev.max())
+
+
+@pytest.mark.parametrize("los", [(0.0, 0.0, 1.0), (1.0, -2.0, 0.5)])
+def test_radial_velocity_records(fb, ora, los):
+    ens = ragged()
+    dt, n_steps, every = TWO_PI / 400, 200, 50
+    say("log RV", los)
+    E = fb.from_gen(ens)
+    t, rv = E.integrate_steps_logged(n_steps, dt, every, kind=fb.LOG_RV, los=los)
+    E.close()
+    ks, ref = oracle_records(ora, ens, dt, n_steps, every)
+    assert rv.shape == (ens.n_sys, len(ks))
+    for r, (k, (x, v)) in enumerate(zip(ks, ref)):
+        assert np.allclose(t[:, r], k * dt, rtol=1e-13, atol=0)
+        want = star_rv(ens, v, los)
+        # the velocity parity bar, per system, carried to one projected component
+        bound = REL_TOL * vel_scale(ens, v) + (1e-14 * vel_scale(ens, v) if r == 0 else 0)
+        err = np.abs(rv[:, r] - want)
+        assert np.all(err <= 2 * bound), (r, int(np.argmax(err / bound)), float((err / bound).max()))
+
+
+def test_energy_records(fb, ora):
+    ens = ragged()
+    dt, n_steps, every = TWO_PI / 400, 200, 100
+    say("log energy")
+    E = fb.from_gen(ens)
+    t, en, L = E.integrate_steps_logged(n_steps, dt, every, kind=fb.LOG_ENERGY)
+    E.close()
+    ks, ref = oracle_records(ora, ens, dt, n_steps, every)
+    for r, (k, (x, v)) in enumerate(zip(ks, ref)):
+        e_ref, l_ref = ora.ensemble_energy(ens.n_body, ens.mass, x, v)
+        # record 0 is the same state on both sides: rounding only; later
+        # records carry the state's 1e-10 through sums with mild cancellation
+        tol = 1e-13 if r == 0 else 2e-9
+        assert np.all(np.abs(en[:, r] - e_ref) <= tol * np.abs(e_ref)), r
+        lmag = np.linalg.norm(l_ref, axis=1)
+        assert np.all(np.linalg.norm(L[:, r] - l_ref, axis=1) <= tol * lmag), r
+
+
+def test_logged_run_ends_bitwise_where_the_unlogged_one_does(fb):
+    ens = ragged()
+    dt = TWO_PI / 300
+    out = []
+    for logged in (False, True):
+        E = fb.from_gen(ens)
+        if logged:
+            E.integrate_steps_logged(333, dt, 41, kind=fb.LOG_RV)
+        else:
+            E.integrate_steps(333, dt)
+        out.append(E.state())
+        E.close()
+    for key in ("pos", "vel", "t", "steps"):
+        assert np.array_equal(out[0][key], out[1][key]), key
+
+
+def test_logging_after_mvs_starts_from_the_inertial_state(fb):
+    ens = gen.paper_ics(64, 4)
+    E = fb.from_gen(ens)
+    E.integrate_mvs(50, TWO_PI / 100)
+    st = E.state()
+    t, pos, vel = E.integrate_steps_logged(0, TWO_PI / 100, 10, kind=fb.LOG_STATE)
+    E.close()
+    assert pos.shape[0] == 1
+    assert np.array_equal(pos[0], st["pos"]) and np.array_equal(vel[0], st["vel"])
+    assert np.array_equal(t[:, 0], st["t"])
+
+
+def test_argument_checks(fb):
+    E = fb.from_gen(gen.three_body(8, seed=62))
+    bad = [lambda: E.integrate_steps_logged(100, 0.01, 10, max_records=5),      # 11 records needed
+           lambda: E.integrate_steps_logged(100, 0.01, 0),
+           lambda: E.integrate_steps_logged(100, 0.01, 10, kind=7, max_records=11),
+           lambda: E.integrate_steps_logged(100, 0.01, 10, los=(0.0, 0.0, 0.0)),
+           lambda: E.integrate_steps_logged(100, 0.01, 10, opts=fb.Opts(schedule=fb.SCHED_PERSISTENT)),
+           lambda: E.integrate_steps_logged(100, 0.01, 10, opts=fb.Opts(adaptive=True))]
+    for f in bad:
+        with pytest.raises(fb.FewbodyError) as ei:
+            f()
+        assert ei.value.code == fb.E_INVAL
+    st0 = E.state()
+    assert np.all(st0["steps"] == 0)           # nothing ran
+    E.close()
