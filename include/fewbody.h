@@ -16,6 +16,13 @@
  * --------------------------------
  * Ensembles are ragged: system s has n_body[s] bodies (2..FB_MAX_BODIES);
  * body 0 of each system is its central star (only the stop rules care).
+ * Systems of up to FB_MAX_SMALL_BODIES bodies run kernels specialised per
+ * body count.  Larger ones run the large-n gravitation (Section 4.2's second
+ * variant: one body per lane across a workgroup, each pair evaluated from
+ * both sides), which takes fixed Hermite steps on the plain schedule only:
+ * adaptive steps, stop rules, the persistent schedule, MVS, Runge-Kutta,
+ * autotuning and the server reject ensembles holding such systems with
+ * FB_E_INVAL.
  * Flat body arrays are body-major: body b of system s is row off[s] + b with
  * off the exclusive prefix sum of n_body; pos/vel/acc/jerk rows hold x,y,z.
  * All floating point is IEEE binary64.
@@ -44,7 +51,8 @@
 extern "C" {
 #endif
 
-#define FB_MAX_BODIES 16
+#define FB_MAX_BODIES 512        /* bodies per system                        */
+#define FB_MAX_SMALL_BODIES 16   /* ... for every integrator and schedule    */
 
 typedef enum {
     FB_OK = 0,
@@ -385,7 +393,8 @@ fb_status fb_server_create(const fb_server_opts *o, void *hip_stream, fb_server 
 size_t fb_server_request_bytes(const fb_server_opts *o, int32_t n_sys, const int32_t *n_body);
 
 /* Queue a request; the host arrays are copied before the call returns
- * (layout as fb_ensemble_create, t0 = 0).  Integrates every system to t_end
+ * (layout as fb_ensemble_create, t0 = 0, 2..FB_MAX_SMALL_BODIES bodies per
+ * system).  Integrates every system to t_end
  * with fixed step dt.  *req_id identifies it.  FB_E_INVAL on bad input,
  * FB_E_BUDGET if it would not fit the budget even on an empty server. */
 fb_status fb_server_submit(fb_server *s, int32_t n_sys, const int32_t *n_body,

@@ -37,7 +37,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORA_MAX_BODIES 64
+#define ORA_MAX_BODIES 512
 
 /* status codes (same meaning as the library's, defined independently) */
 enum {

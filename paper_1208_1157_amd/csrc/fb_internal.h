@@ -20,7 +20,8 @@ enum SysStatus {
 
 enum Mapping { MAP_SPL = 1, MAP_BPL = 2 };
 
-constexpr int kMaxBodies = 16;
+constexpr int kMaxBodies = 16;         // kernels specialised per n exist for n <= 16
+constexpr int kMaxLargeBodies = 512;   // larger systems run the runtime-n large-n kernels
 constexpr int kMaxSplBodies = 10;      // plain system-per-lane instances exist for n <= 10
 constexpr int kMaxSplAdv = 5;          // ... with adaptive steps / stop rules for n <= 5
 constexpr int kMaxSplPersistent = 0;   // the body-per-lane fused class runs no system-per-lane tiles
@@ -126,6 +127,10 @@ hipError_t launch_unpack_mvs(const Bucket &B, const long long *orig_off, double 
                              double *vel, double *t, int *status, long long *steps,
                              hipStream_t s);
 hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s);
+// Workgroup shape of the large-n kernels (n > kMaxBodies): T lanes, a
+// multiple of 64 up to 512, holding S = floor(T / n) systems of one body per
+// lane; the T that leaves the fewest lanes idle.  S = 0 if n > 512.
+void large_shape(int n, int &T, int &S);
 // FP64 FMA issue-ceiling probe: blocks x 256 lanes, iters x kFmaChains FMAs
 // per lane (kFmaChains = 16); out holds blocks x 256 doubles.
 hipError_t launch_fma_probe(double *out, int blocks, int iters, hipStream_t s);

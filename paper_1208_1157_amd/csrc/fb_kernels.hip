@@ -1148,16 +1148,15 @@ __global__ void k_prepare(Bucket B)
 // t_end, with fixed dt or (adaptive) the carried step, proposing one from
 // the current state when none is carried yet.  Systems stopped by a rule
 // keep their status.
-template <int N>
-__global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double t_end,
-                            double dt, int adaptive, double eta)
+// The clock part of a run's start for slot s; true when an adaptive step
+// (rule 1 or 2) must still be proposed from the system's state.
+__device__ __forceinline__ bool begin_run_clock(const Bucket &B, const int s, int fixed_steps,
+                                                long long n_steps, double t_end, double dt,
+                                                int adaptive)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= B.count)
-        return;
     const int st = B.status[s];
     if (st != ST_ACTIVE && st != ST_DONE && st != ST_MAXSTEPS)
-        return;
+        return false;
     const double t = B.t[s];
     B.t0run[s] = t;
     B.krun[s] = 0;
@@ -1166,7 +1165,7 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
         B.nfull[s] = n_steps;
         B.t_end[s] = fma((double)n_steps, dt, t);
         B.status[s] = n_steps > 0 ? ST_ACTIVE : ST_DONE;
-        return;
+        return false;
     }
     B.t_end[s] = t_end;
     if (adaptive == 3) {   // Runge-Kutta Cash-Karp: dt is the first trial step
@@ -1174,7 +1173,7 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
         B.dt[s] = 0.0;
         B.dtn[s] = dt;
         B.status[s] = t < t_end ? ST_ACTIVE : ST_DONE;
-        return;
+        return false;
     }
     if (adaptive) {
         B.nfull[s] = 0;
@@ -1183,26 +1182,7 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
         // Eq. 5's step depends only on the stored (a0, j0), so it is always
         // recomputed (identical to the carried value); the pairwise rule's
         // carried step comes from the last evaluation's state and is kept.
-        if (adaptive == 2 || !(B.dtn[s] > 0.0)) {
-            double m[N], x[N][3], v[N][3], a[N][3], jk[N][3];
-            load_xv<N>(B, s, m, x, v);
-            if (adaptive == 2) {
-                const size_t pitch = B.pitch;
-#pragma unroll
-                for (int b = 0; b < N; ++b)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        a[b][c] = B.st[((R_A + c) * N + b) * pitch + s];
-                        jk[b][c] = B.st[((R_J + c) * N + b) * pitch + s];
-                    }
-                B.dtn[s] = paper_dt<N>(a, jk, eta);
-            } else {
-                double w = 0.0;
-                spl_accjerk<N, true>(m, x, v, a, jk, w);
-                B.dtn[s] = eta * rsqrt_nr(w);
-            }
-        }
-        return;
+        return adaptive == 2 || !(B.dtn[s] > 0.0);
     }
     B.dt[s] = dt;
     const double span = (t_end - t) / dt;
@@ -1211,6 +1191,44 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
         --nf;
     B.nfull[s] = nf;
     B.status[s] = (t_end - t) * dt > 0.0 ? ST_ACTIVE : ST_DONE;
+    return false;
+}
+
+template <int N>
+__global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double t_end,
+                            double dt, int adaptive, double eta)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    if (!begin_run_clock(B, s, fixed_steps, n_steps, t_end, dt, adaptive))
+        return;
+    double m[N], x[N][3], v[N][3], a[N][3], jk[N][3];
+    load_xv<N>(B, s, m, x, v);
+    if (adaptive == 2) {
+        const size_t pitch = B.pitch;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[b][c] = B.st[((R_A + c) * N + b) * pitch + s];
+                jk[b][c] = B.st[((R_J + c) * N + b) * pitch + s];
+            }
+        B.dtn[s] = paper_dt<N>(a, jk, eta);
+    } else {
+        double w = 0.0;
+        spl_accjerk<N, true>(m, x, v, a, jk, w);
+        B.dtn[s] = eta * rsqrt_nr(w);
+    }
+}
+
+// Run start of a large-n bucket (fixed steps only).
+__global__ void k_begin_run_large(Bucket B, int fixed_steps, long long n_steps, double t_end,
+                                  double dt)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < B.count)
+        (void)begin_run_clock(B, s, fixed_steps, n_steps, t_end, dt, 0);
 }
 
 // bucket SoA -> AoS rows in caller order (any output may be null).
@@ -1928,6 +1946,382 @@ void k_plain_rkck(Bucket B, StepParams P, double eps)
     }
 }
 
+// ---------------------------------------------------------------------------
+// large systems (n > 16): one body per lane across a whole workgroup
+// ---------------------------------------------------------------------------
+// Section 4.2's second gravitation variant, for larger n.  Every lane owns
+// one body and sums all n-1 of that body's interactions itself, so each pair
+// is evaluated twice (once from either side) and the workgroup's LDS holds
+// only the bodies' evaluation state, never per-pair terms.  S = floor(T / n)
+// systems share a workgroup of T lanes (lane = system * n + body); a body's
+// partners are LDS broadcasts to the lanes of its system.  Two copies of the
+// evaluation state alternate, so an evaluation costs one workgroup barrier: a
+// lane overwrites a copy only after the next evaluation's barrier, which
+// every reader of that copy has passed.
+
+// Lanes of the largest large-n workgroup (its LDS stays below 64 KiB).
+constexpr int kLargeMaxLanes = 512;
+
+// Dynamic LDS of a large-n workgroup of T lanes: two copies of the
+// evaluation state (three 16-byte pairs per lane each), the masses and one
+// int per lane.
+__host__ __device__ constexpr size_t large_lds_bytes(int T)
+{
+    return (size_t)T * (6 * sizeof(double2) + sizeof(double) + sizeof(int));
+}
+
+struct LargeView {
+    double2 *xy, *zvx, *vyvz;   // copy c of lane l at [c * T + l]
+    double *m;
+    int *flag;
+};
+
+__device__ __forceinline__ LargeView large_view(const int T)
+{
+    extern __shared__ char fb_dyn_lds[];
+    double2 *p = reinterpret_cast<double2 *>(fb_dyn_lds);
+    LargeView V;
+    V.xy = p;
+    V.zvx = p + 2 * T;
+    V.vyvz = p + 4 * T;
+    V.m = reinterpret_cast<double *>(p + 6 * T);
+    V.flag = reinterpret_cast<int *>(V.m + T);
+    return V;
+}
+
+// One interaction of body i with the partner at LDS index idx of one copy
+// (Eq. 1 and its time derivative; the terms of bpl_interact).
+__device__ __forceinline__ void large_interact(const double2 *__restrict__ xy,
+                                               const double2 *__restrict__ zvx,
+                                               const double2 *__restrict__ vyvz,
+                                               const double *__restrict__ mm, const int idx,
+                                               const double (&xi)[3], const double (&vi)[3],
+                                               double (&a)[3], double (&jk)[3])
+{
+    const double2 p0 = xy[idx];
+    const double2 p1 = zvx[idx];
+    const double2 p2 = vyvz[idx];
+    const double mj = mm[idx];
+    const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
+    const double ux = p1.y - vi[0], uy = p2.x - vi[1], uz = p2.y - vi[2];
+    const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+    const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
+    const double ri = rsqrt_nr(r2);
+    const double ri2 = ri * ri;
+    const double mr3 = mj * (ri2 * ri);
+    const double al = 3.0 * ru * ri2;
+    a[0] = fma(mr3, rx, a[0]);
+    a[1] = fma(mr3, ry, a[1]);
+    a[2] = fma(mr3, rz, a[2]);
+    jk[0] = fma(mr3, fma(-al, rx, ux), jk[0]);
+    jk[1] = fma(mr3, fma(-al, ry, uy), jk[1]);
+    jk[2] = fma(mr3, fma(-al, rz, uz), jk[2]);
+}
+
+// Publish this lane's state in copy `cp`, wait for the workgroup, and (live
+// lanes) sum the body's interactions: the other planets in ascending order,
+// then the star (the star's lane sums planets 1..n-1).
+__device__ __forceinline__ void large_eval(const LargeView &V, const int T, const int cp,
+                                           const int tid, const int base, const int b,
+                                           const int n, const bool live, const double (&xi)[3],
+                                           const double (&vi)[3], double (&a)[3],
+                                           double (&jk)[3])
+{
+    const double2 *xy = V.xy + cp * T;
+    const double2 *zvx = V.zvx + cp * T;
+    const double2 *vyvz = V.vyvz + cp * T;
+    V.xy[cp * T + tid] = make_double2(xi[0], xi[1]);
+    V.zvx[cp * T + tid] = make_double2(xi[2], vi[0]);
+    V.vyvz[cp * T + tid] = make_double2(vi[1], vi[2]);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a[c] = 0.0;
+        jk[c] = 0.0;
+    }
+    if (!live)
+        return;
+    const int skip = b == 0 ? INT_MAX : b;
+#pragma unroll 4
+    for (int k = 0; k < n - 2; ++k) {
+        const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
+        large_interact(xy, zvx, vyvz, V.m, base + j, xi, vi, a, jk);
+    }
+    large_interact(xy, zvx, vyvz, V.m, base + (b == 0 ? n - 1 : 0), xi, vi, a, jk);
+}
+
+// Lane geometry of a large-n workgroup.
+struct LargeLane {
+    int tid, sys, b, base, slot;
+    bool valid;
+};
+
+__device__ __forceinline__ LargeLane large_lane(const Bucket &B, const int S)
+{
+    LargeLane l;
+    l.tid = threadIdx.x;
+    l.sys = l.tid / B.n;
+    l.b = l.tid - l.sys * B.n;
+    l.base = l.sys * B.n;
+    const int slot = blockIdx.x * S + l.sys;
+    l.valid = l.sys < S && slot < B.count;
+    l.slot = l.valid ? slot : 0;
+    return l;
+}
+
+// Fixed Hermite P(EC)^2 steps of S systems per workgroup for at most
+// P.quantum steps (Algorithm 1's loop, Algorithm 2's step).
+__global__ __launch_bounds__(kLargeMaxLanes) void k_plain_large(Bucket B, StepParams P, int S)
+{
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    const size_t pitch = B.pitch;
+    double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
+    Clock c;
+    c.status = ST_DONE;
+    if (l.valid) {
+        mi = B.st[(R_M * n + l.b) * pitch + l.slot];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            x[cc] = B.st[((R_X + cc) * n + l.b) * pitch + l.slot];
+            v[cc] = B.st[((R_V + cc) * n + l.b) * pitch + l.slot];
+            a0[cc] = B.st[((R_A + cc) * n + l.b) * pitch + l.slot];
+            j0[cc] = B.st[((R_J + cc) * n + l.b) * pitch + l.slot];
+        }
+        c = load_clock(B, l.slot);
+    }
+    V.m[l.tid] = mi;   // ordered before any read by the loop's first barrier
+    for (int q = 0; q < P.quantum; ++q) {
+        double h = 0.0;
+        bool last = false;
+        const bool act = l.valid && plan_step(c, P, h, last);
+        if (!__syncthreads_or(act))
+            break;
+        const Coef k = make_coef(h);
+        double xc[3], vc[3], bx[3], bv[3], ak[3], jk[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            predict_comp(k, x[cc], v[cc], a0[cc], j0[cc], xc[cc], vc[cc], bx[cc], bv[cc]);
+        large_eval(V, T, 0, l.tid, l.base, l.b, n, l.valid, xc, vc, ak, jk);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
+        large_eval(V, T, 1, l.tid, l.base, l.b, n, l.valid, xc, vc, ak, jk);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
+        if (act) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                x[cc] = xc[cc];
+                v[cc] = vc[cc];
+                a0[cc] = ak[cc];
+                j0[cc] = jk[cc];
+            }
+            finish_step(c, P, last, h, 0.0);
+        }
+    }
+    V.flag[l.tid] = (l.valid && !(finite3(x) && finite3(v))) ? 1 : 0;
+    __syncthreads();
+    if (!l.valid)
+        return;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        B.st[((R_X + cc) * n + l.b) * pitch + l.slot] = x[cc];
+        B.st[((R_V + cc) * n + l.b) * pitch + l.slot] = v[cc];
+        B.st[((R_A + cc) * n + l.b) * pitch + l.slot] = a0[cc];
+        B.st[((R_J + cc) * n + l.b) * pitch + l.slot] = j0[cc];
+    }
+    if (l.b == 0) {
+        int fl = 0;
+        for (int k = 0; k < n; ++k)
+            fl |= V.flag[l.base + k];
+        if (fl)
+            c.status = ST_NONFINITE;
+        store_clock(B, l.slot, c);
+    }
+}
+
+// Algorithm 1's "prepare" for large n: (a0, j0) at the current state.
+__global__ __launch_bounds__(kLargeMaxLanes) void k_prepare_large(Bucket B, int S)
+{
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    const size_t pitch = B.pitch;
+    double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    if (l.valid) {
+        mi = B.st[(R_M * n + l.b) * pitch + l.slot];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            x[cc] = B.st[((R_X + cc) * n + l.b) * pitch + l.slot];
+            v[cc] = B.st[((R_V + cc) * n + l.b) * pitch + l.slot];
+        }
+    }
+    V.m[l.tid] = mi;
+    double a[3], jk[3];
+    large_eval(V, T, 0, l.tid, l.base, l.b, n, l.valid, x, v, a, jk);
+    if (!l.valid)
+        return;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        B.st[((R_A + cc) * n + l.b) * pitch + l.slot] = a[cc];
+        B.st[((R_J + cc) * n + l.b) * pitch + l.slot] = jk[cc];
+    }
+}
+
+// Per-system sums over the bodies of a large-n workgroup, in body order, on
+// the star's lane: lane values q[0..4] go through copy 1 of the state arrays.
+__device__ __forceinline__ void large_sum5(const LargeView &V, const int T, const LargeLane &l,
+                                           const int n, const double (&q)[5], double (&out)[5])
+{
+    double2 *r0 = V.xy + T, *r1 = V.zvx + T, *r2 = V.vyvz + T;
+    r0[l.tid] = make_double2(q[0], q[1]);
+    r1[l.tid] = make_double2(q[2], q[3]);
+    r2[l.tid] = make_double2(q[4], 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        out[c] = 0.0;
+    if (!l.valid || l.b != 0)
+        return;
+    for (int k = 0; k < n; ++k) {
+        const double2 p = r0[l.base + k], u = r1[l.base + k], w = r2[l.base + k];
+        out[0] += p.x;
+        out[1] += p.y;
+        out[2] += u.x;
+        out[3] += u.y;
+        out[4] += w.x;
+    }
+}
+
+// Energy (Eq. 6) and angular momentum parts of this lane's body: its kinetic
+// energy, the potential of its pairs with higher-numbered partners (each pair
+// once) and m x cross v.
+__device__ __forceinline__ void large_energy_terms(const LargeView &V, const int T,
+                                                   const LargeLane &l, const int n,
+                                                   const double mi, const double (&x)[3],
+                                                   const double (&v)[3], double (&q)[5])
+{
+    V.m[l.tid] = mi;
+    V.xy[l.tid] = make_double2(x[0], x[1]);
+    V.zvx[l.tid] = make_double2(x[2], 0.0);
+    __syncthreads();
+    double pot = 0.0;
+    if (l.valid)
+        for (int j = l.b + 1; j < n; ++j) {
+            const double2 p0 = V.xy[l.base + j], p1 = V.zvx[l.base + j];
+            const double dx = x[0] - p0.x, dy = x[1] - p0.y, dz = x[2] - p1.x;
+            pot += V.m[l.base + j] / sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+        }
+    q[0] = 0.5 * mi * fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0])) - mi * pot;
+    q[1] = 0.0;
+    q[2] = mi * (x[1] * v[2] - x[2] * v[1]);
+    q[3] = mi * (x[2] * v[0] - x[0] * v[2]);
+    q[4] = mi * (x[0] * v[1] - x[1] * v[0]);
+}
+
+__device__ __forceinline__ void large_load_xv(const Bucket &B, const LargeLane &l, double &mi,
+                                              double (&x)[3], double (&v)[3])
+{
+    mi = 0.0;
+    const size_t pitch = B.pitch;
+    const int n = B.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = 0.0;
+        v[c] = 0.0;
+    }
+    if (!l.valid)
+        return;
+    mi = B.st[(R_M * n + l.b) * pitch + l.slot];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = B.st[((R_X + c) * n + l.b) * pitch + l.slot];
+        v[c] = B.st[((R_V + c) * n + l.b) * pitch + l.slot];
+    }
+}
+
+// Energy and angular momentum of every system of a large-n bucket.
+__global__ __launch_bounds__(kLargeMaxLanes) void k_diag_large(Bucket B, int S, double *energy,
+                                                     double *angmom)
+{
+    const int T = blockDim.x;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    double mi, x[3], v[3], q[5], sum[5];
+    large_load_xv(B, l, mi, x, v);
+    large_energy_terms(V, T, l, B.n, mi, x, v, q);
+    large_sum5(V, T, l, B.n, q, sum);
+    if (!l.valid || l.b != 0)
+        return;
+    const int o = B.orig[l.slot];
+    if (energy)
+        energy[o] = sum[0];
+    if (angmom) {
+        angmom[3 * o + 0] = sum[2];
+        angmom[3 * o + 1] = sum[3];
+        angmom[3 * o + 2] = sum[4];
+    }
+}
+
+// Monitor record k of every system of a large-n bucket (layouts of k_log).
+__global__ __launch_bounds__(kLargeMaxLanes) void k_log_large(Bucket B, int S,
+                                                    const long long *__restrict__ orig_off,
+                                                    int kind, double lx, double ly, double lz,
+                                                    int k, int max_records, double *out)
+{
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    double mi, x[3], v[3], q[5], sum[5];
+    large_load_xv(B, l, mi, x, v);
+    const int o = l.valid ? B.orig[l.slot] : 0;
+    const double t = l.valid ? B.t[l.slot] : 0.0;
+    if (kind == 0) {
+        if (!l.valid)
+            return;
+        double *r = out + (size_t)max_records * ((size_t)o + 6 * (size_t)orig_off[o]) +
+                    (size_t)k * (1 + 6 * n);
+        if (l.b == 0)
+            r[0] = t;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r[1 + 3 * l.b + c] = x[c];
+            r[1 + 3 * n + 3 * l.b + c] = v[c];
+        }
+        return;
+    }
+    if (kind == 1) {
+        q[0] = mi;
+        q[1] = mi * v[0];
+        q[2] = mi * v[1];
+        q[3] = mi * v[2];
+        q[4] = 0.0;
+    } else {
+        large_energy_terms(V, T, l, n, mi, x, v, q);
+    }
+    large_sum5(V, T, l, n, q, sum);
+    if (!l.valid || l.b != 0)
+        return;
+    if (kind == 1) {
+        const double rv = fma(v[2] - sum[3] / sum[0], lz,
+                              fma(v[1] - sum[2] / sum[0], ly, (v[0] - sum[1] / sum[0]) * lx));
+        double *r = out + ((size_t)o * max_records + k) * 2;
+        r[0] = t;
+        r[1] = rv;
+    } else {
+        double *r = out + ((size_t)o * max_records + k) * 5;
+        r[0] = t;
+        r[1] = sum[0];
+        r[2] = sum[2];
+        r[3] = sum[3];
+        r[4] = sum[4];
+    }
+}
+
 // FP64 issue-ceiling probe for the roofline: each lane runs kFmaChains
 // independent FMA chains (a <- a*b + c, b slightly below 1 so values stay
 // bounded), so the rate is set by VALU issue rather than FMA latency.
@@ -1980,10 +2374,49 @@ hipError_t launch_pack(const Bucket &B, const double *mass, const double *pos,
     return hipGetLastError();
 }
 
+void large_shape(int n, int &T, int &S)
+{
+    T = 0;
+    S = 0;
+    long long best_used = -1, best_T = 1;
+    for (int t = 64; t <= kLargeMaxLanes; t += 64) {
+        const int s = t / n;
+        if (s < 1)
+            continue;
+        // more of the lanes in use (s n / t), compared exactly; ties keep the smaller t
+        if ((long long)s * n * best_T > best_used * t) {
+            best_used = (long long)s * n;
+            best_T = t;
+            T = t;
+            S = s;
+        }
+    }
+}
+
+namespace {
+// Launch geometry of a large-n bucket: grid, lanes, systems per workgroup.
+bool large_launch(const Bucket &B, dim3 &grid, int &T, int &S)
+{
+    large_shape(B.n, T, S);
+    if (S < 1)
+        return false;
+    grid = dim3((unsigned)((B.count + S - 1) / S));
+    return true;
+}
+}  // namespace
+
 hipError_t launch_prepare(const Bucket &B, hipStream_t s)
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxBodies) {
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_prepare_large, grid, dim3(T), large_lds_bytes(T), s, B, S);
+        return hipGetLastError();
+    }
 #define FB_L(NN) hipLaunchKernelGGL(k_prepare<NN>, grid_for(B.count, 64), dim3(64), 0, s, B)
     FB_SWITCH_N(B.n, FB_L)
 #undef FB_L
@@ -1995,6 +2428,13 @@ hipError_t launch_begin_run(const Bucket &B, int fixed_steps, long long n_steps,
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxBodies) {
+        if (!fixed_steps && adaptive)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_begin_run_large, grid_for(B.count, 64), dim3(64), 0, s, B,
+                           fixed_steps, n_steps, t_end, dt);
+        return hipGetLastError();
+    }
 #define FB_L(NN)                                                                        \
     hipLaunchKernelGGL(k_begin_run<NN>, grid_for(B.count, 64), dim3(64), 0, s, B,       \
                        fixed_steps, n_steps, t_end, dt, adaptive, eta)
@@ -2010,6 +2450,14 @@ hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const
         return hipSuccess;
     const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
     const bool adv = P.adaptive || P.stop_rules;
+    if (B.n > kMaxBodies) {
+        dim3 grid;
+        int T, S;
+        if (adv || !large_launch(B, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_plain_large, grid, dim3(T), large_lds_bytes(T), s, B, P, S);
+        return hipGetLastError();
+    }
     if (mapping == MAP_SPL && B.n <= (adv ? kMaxSplAdv : kMaxSplBodies)) {
         const dim3 grid = grid_for(B.count, 64 * W);
 #define FB_LA(NN)                                                                       \
@@ -2141,6 +2589,15 @@ hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxBodies) {
+        dim3 grid;
+        int T, S;
+        if (mvs_form || !large_launch(B, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_diag_large, grid, dim3(T), large_lds_bytes(T), s, B, S, energy,
+                           angmom);
+        return hipGetLastError();
+    }
     if (mvs_form) {
         if (B.n > kMaxMvsBodies)
             return hipErrorInvalidValue;
@@ -2222,6 +2679,15 @@ hipError_t launch_log(const Bucket &B, const long long *orig_off, int kind, cons
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxBodies) {
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_log_large, grid, dim3(T), large_lds_bytes(T), s, B, S, orig_off,
+                           kind, los[0], los[1], los[2], k, max_records, out);
+        return hipGetLastError();
+    }
 #define FB_L(NN) hipLaunchKernelGGL(k_log<NN>, grid_for(B.count, 64), dim3(64), 0, s, B, orig_off, \
                                     kind, los[0], los[1], los[2], k, max_records, out)
     FB_SWITCH_N(B.n, FB_L)

@@ -124,10 +124,10 @@ bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L)
 {
     if (n_sys < 0 || (n_sys > 0 && !n_body))
         return false;
-    int cnt[kMaxBodies + 1] = {0};
+    std::vector<int> cnt(kMaxLargeBodies + 1, 0);
     int64_t nb = 0;
     for (int s = 0; s < n_sys; ++s) {
-        if (n_body[s] < 2 || n_body[s] > kMaxBodies)
+        if (n_body[s] < 2 || n_body[s] > kMaxLargeBodies)
             return false;
         cnt[n_body[s]]++;
         nb += n_body[s];
@@ -141,7 +141,7 @@ bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L)
     };
     L.max_tiles = 0;
     L.list_total = 0;
-    for (int n = kMaxBodies; n >= 2; --n) {   // buckets in descending n: longest work first
+    for (int n = kMaxLargeBodies; n >= 2; --n) {   // buckets in descending n: longest work first
         if (!cnt[n])
             continue;
         BucketLayout bl;
@@ -160,7 +160,8 @@ bool make_layout(int32_t n_sys, const int32_t *n_body, Layout &L)
         bl.steps = take(8 * P);
         bl.status = take(4 * P);
         bl.orig = take(4 * P);
-        L.max_tiles += (cnt[n] + (64 / n) - 1) / (64 / n);
+        const int per_tile = std::max(1, 64 / n);
+        L.max_tiles += (cnt[n] + per_tile - 1) / per_tile;
         L.list_total += bl.pitch;
         L.b.push_back(bl);
     }
@@ -413,7 +414,7 @@ fb_status run_plain(fb_ensemble *e, const fb_opts &o, long long step_bound)
     const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
     for (;;) {
         for (const Bucket &B : e->buckets) {
-            const Plan p = get_plan(B.n);
+            const Plan p = B.n <= kMaxBodies ? get_plan(B.n) : Plan{MAP_BPL, 1, 0};
             const StepParams P = make_params(o, quantum);
             const int map = plain_mapping(p, B, P.adaptive || P.stop_rules, e->num_cu);
             ProfScope ps(e->stream);
@@ -630,6 +631,24 @@ fb_status run_rkck(fb_ensemble *e, const fb_opts &o, int adaptive, double eps,
     }
 }
 
+bool has_large(const fb_ensemble *e)
+{
+    for (const Bucket &B : e->buckets)
+        if (B.n > kMaxBodies)
+            return true;
+    return false;
+}
+
+// Systems of more than kMaxBodies bodies run the large-n kernels: fixed
+// Hermite steps on the plain schedule.
+fb_status check_large(const fb_ensemble *e, const fb_opts &o)
+{
+    if (has_large(e) && (o.adaptive || o.stop_rules || o.schedule != FB_SCHED_PLAIN))
+        return fail(FB_E_INVAL, "systems of more than %d bodies take fixed steps on the plain "
+                                "schedule without stop rules", kMaxBodies);
+    return FB_OK;
+}
+
 fb_status check_rk_opts(const fb_opts &o)
 {
     if (o.adaptive || o.stop_rules || o.compact || o.schedule != FB_SCHED_PLAIN)
@@ -702,7 +721,7 @@ fb_status fb_ensemble_create(int32_t n_sys, const int32_t *n_body, const double 
     *out = nullptr;
     Layout L;
     if (!make_layout(n_sys, n_body, L))
-        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxBodies);
+        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxLargeBodies);
     const size_t N = (size_t)L.n_bodies;
     if (N && (!mass || !pos || !vel))
         return fail(FB_E_INVAL, "mass, pos and vel are required");
@@ -762,7 +781,7 @@ fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body, const 
     *out = nullptr;
     Layout L;
     if (!make_layout(n_sys, n_body, L))
-        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxBodies);
+        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxLargeBodies);
     if (L.n_bodies && (!d_mass || !d_pos || !d_vel))
         return fail(FB_E_INVAL, "d_mass, d_pos and d_vel are required");
     if (!d_workspace || ws_bytes < L.total)
@@ -805,6 +824,9 @@ fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt, const f
     if (!(std::isfinite(dt) && dt != 0.0))
         return fail(FB_E_INVAL, "dt must be finite and non-zero");
     fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    st = check_large(e, o);
     if (st != FB_OK)
         return st;
     if (n_steps == 0 || e->n_sys == 0)
@@ -857,7 +879,7 @@ size_t fb_log_bytes(int32_t n_sys, const int32_t *n_body, int32_t kind, int32_t 
         return 0;
     size_t bodies = 0;
     for (int32_t s = 0; s < n_sys; ++s) {
-        if (n_body[s] < 2 || n_body[s] > kMaxBodies)
+        if (n_body[s] < 2 || n_body[s] > kMaxLargeBodies)
             return 0;
         bodies += (size_t)n_body[s];
     }
@@ -886,6 +908,9 @@ fb_status fb_integrate_steps_logged(fb_ensemble *e, int64_t n_steps, double dt, 
     if (o.schedule != FB_SCHED_PLAIN)
         return fail(FB_E_INVAL, "logged integration runs the plain schedule");
     fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    st = check_large(e, o);
     if (st != FB_OK)
         return st;
     if (n_steps < 0 || !(std::isfinite(dt) && dt != 0.0))
@@ -952,6 +977,8 @@ fb_status fb_integrate_rkck_steps(fb_ensemble *e, int64_t n_steps, double dt, co
     fb_status st = check_rk_opts(o);
     if (st != FB_OK)
         return st;
+    if (has_large(e))
+        return fail(FB_E_INVAL, "Runge-Kutta runs systems of at most %d bodies", kMaxBodies);
     if (n_steps < 0)
         return fail(FB_E_INVAL, "n_steps must be >= 0");
     if (!(std::isfinite(dt) && dt != 0.0))
@@ -979,6 +1006,8 @@ fb_status fb_integrate_rkck(fb_ensemble *e, double t_end, double dt, double eps,
     fb_status st = check_rk_opts(o);
     if (st != FB_OK)
         return st;
+    if (has_large(e))
+        return fail(FB_E_INVAL, "Runge-Kutta runs systems of at most %d bodies", kMaxBodies);
     if (!std::isfinite(t_end))
         return fail(FB_E_INVAL, "t_end must be finite");
     if (!(std::isfinite(dt) && dt > 0.0))
@@ -1005,6 +1034,9 @@ fb_status fb_integrate(fb_ensemble *e, double t_end, double dt, const fb_opts *p
     if (po)
         o = *po;
     fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    st = check_large(e, o);
     if (st != FB_OK)
         return st;
     if (!std::isfinite(t_end))
@@ -1183,6 +1215,8 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         *n_out = 0;
     if (e->n_sys == 0)
         return FB_OK;
+    if (has_large(e))
+        return fail(FB_E_INVAL, "autotuning covers systems of at most %d bodies", kMaxBodies);
     fb_status st0 = ensure_inertial(e);
     if (st0 != FB_OK)
         return st0;

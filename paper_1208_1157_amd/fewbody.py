@@ -35,7 +35,8 @@ MAX_MVS_BODIES = 8
 STOP_ENCOUNTER, STOP_EJECT = 1, 2
 MAP_AUTO, MAP_SPL, MAP_BPL = 0, 1, 2
 SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
-MAX_BODIES = 16
+MAX_BODIES = 512         # bodies per system
+MAX_SMALL_BODIES = 16    # ... for every integrator and schedule (larger: fixed Hermite steps, plain schedule)
 
 
 class FbOpts(ctypes.Structure):
@@ -247,7 +248,7 @@ class Ensemble:
             t = dtensor(t0, (-1,))
         ws = workspace_bytes(self.n_body)
         if ws == 0 and self.n_sys > 0:
-            raise FewbodyError(E_INVAL, "invalid body counts (each must be 2..16)")
+            raise FewbodyError(E_INVAL, f"invalid body counts (each must be 2..{MAX_BODIES})")
         raw = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
         addr = raw.data_ptr()
         aligned = (addr + 255) // 256 * 256

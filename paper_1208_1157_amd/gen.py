@@ -147,6 +147,8 @@ def _draw_planets(rng, n_body, mlo, mhi, e_hi, inc_deg_hi, spacing):
     if spacing == "two-planet":
         a = np.ones(shape)
         a[:, 1] = rng.uniform(1.5, 3.0, n_sys)
+    elif spacing[0] == "annulus":
+        a = rng.uniform(spacing[1], spacing[2], shape)
     else:
         a = _hill_spaced(rng, m_pl, valid, *spacing)
     e = rng.uniform(0.0, e_hi, shape)
@@ -173,6 +175,17 @@ def ragged_hill(n_sys: int, seed: int, n_lo=3, n_hi=15, mlo=1e-6, mhi=1e-4,
     n_body = rng.integers(n_lo, n_hi + 1, n_sys).astype(np.int32)
     ens = _draw_planets(rng, n_body, mlo, mhi, e_hi, inc_deg_hi, (k_lo, k_hi))
     ens.meta = {"family": "ragged_hill", "seed": seed, "n_range": [n_lo, n_hi]}
+    return ens
+
+
+def planetesimal_disk(n_sys: int, n: int, seed: int, mlo=1e-9, mhi=1e-7, a_lo=1.0, a_hi=3.0,
+                      e_hi=0.02, inc_deg_hi=1.0) -> Ensemble:
+    """Star + (n-1) small bodies (large-n systems): m ~ logU[mlo, mhi], a ~ U[a_lo, a_hi],
+    e ~ U[0, e_hi], i ~ U[0, inc_deg_hi deg], node/peri/M ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    n_body = np.full(n_sys, n, dtype=np.int32)
+    ens = _draw_planets(rng, n_body, mlo, mhi, e_hi, inc_deg_hi, ("annulus", a_lo, a_hi))
+    ens.meta = {"family": "planetesimal_disk", "seed": seed, "n": n}
     return ens
 
 
@@ -212,6 +225,10 @@ def workload(name: str, n_sys: int | None = None):
         ens = ragged_hill(n_sys or 65536, seed=3, n_lo=4, n_hi=8, mlo=1e-5, mhi=1e-3,
                           k_lo=3.0, k_hi=6.0, e_hi=0.2, inc_deg_hi=1.0)
         return ens, {"eta": 0.01, "t_end": TWO_PI * 1e4, "r_eject": 100.0}
+    if name.startswith("disk_"):          # disk_<n_sys>x<n>: large-n planetesimal disks
+        ns, n = (int(v) for v in name[5:].split("x"))
+        ens = planetesimal_disk(n_sys or ns, n, seed=5)
+        return ens, {"dt": H_INNER_1000, "steps": 1000}
     raise KeyError(name)
 
 

@@ -47,7 +47,8 @@ def test_workspace_bytes(fbmod):
     assert fbmod.workspace_bytes([3, 3, 5]) > 0
     assert fbmod.workspace_bytes([]) > 0
     assert fbmod.workspace_bytes([1]) == 0          # n_body below 2
-    assert fbmod.workspace_bytes([17]) == 0         # n_body above 16
+    assert fbmod.workspace_bytes([513]) == 0        # n_body above 512
+    assert fbmod.workspace_bytes([17, 300]) > 0     # large-n systems
     a = fbmod.workspace_bytes([3] * 1000)
     b = fbmod.workspace_bytes([3] * 2000)
     assert b > a
@@ -75,7 +76,7 @@ def test_create_rejects_bad_input_before_device_work(fbmod):
     assert rc == fbmod.E_INVAL and b"finite" in fbmod.lib().fb_last_error()
     rc, _ = _create(fbmod, [1, 2], m, x, v)
     assert rc == fbmod.E_INVAL
-    rc, _ = _create(fbmod, [17], np.ones(17), np.zeros((17, 3)), np.zeros((17, 3)))
+    rc, _ = _create(fbmod, [513], np.ones(513), np.zeros((513, 3)), np.zeros((513, 3)))
     assert rc == fbmod.E_INVAL
 
 
@@ -147,7 +148,7 @@ def test_log_bytes(fbmod):
     assert fbmod.log_bytes(nb, fbmod.LOG_STATE, R) == 8 * R * sum(1 + 6 * n for n in nb)
     assert fbmod.log_bytes(nb, 3, R) == 0
     assert fbmod.log_bytes(nb, fbmod.LOG_RV, 0) == 0
-    assert fbmod.log_bytes([3, 17], fbmod.LOG_RV, R) == 0
+    assert fbmod.log_bytes([3, 513], fbmod.LOG_RV, R) == 0
     assert fbmod.log_bytes([], fbmod.LOG_STATE, R) == 0
 
 
