@@ -127,10 +127,13 @@ hipError_t launch_unpack_mvs(const Bucket &B, const long long *orig_off, double 
                              double *vel, double *t, int *status, long long *steps,
                              hipStream_t s);
 hipError_t launch_count_active(const Bucket &B, int *count, hipStream_t s);
-// Workgroup shape of the large-n kernels (n > kMaxBodies): T lanes, a
-// multiple of 64 up to 512, holding S = floor(T / n) systems of one body per
-// lane; the T that leaves the fewest lanes idle.  S = 0 if n > 512.
-void large_shape(int n, int &T, int &S);
+// Workgroup shape of the large-n kernels (n > kMaxBodies) with k bodies per
+// lane: T lanes, a multiple of 64 up to 512 / k, holding S = floor(T / H)
+// systems of H = ceil(n / k) lanes each; the T that leaves the fewest lanes
+// idle.  S = 0 if the system does not fit.
+void large_shape(int n, int k, int &T, int &S);
+// Bodies per lane (1 or 2) of the large-n step kernel for n-body systems.
+int large_bodies_per_lane(int n);
 // FP64 FMA issue-ceiling probe: blocks x 256 lanes, iters x kFmaChains FMAs
 // per lane (kFmaChains = 16); out holds blocks x 256 doubles.
 hipError_t launch_fma_probe(double *out, int blocks, int iters, hipStream_t s);

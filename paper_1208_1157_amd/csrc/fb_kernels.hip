@@ -2069,78 +2069,226 @@ __device__ __forceinline__ LargeLane large_lane(const Bucket &B, const int S)
     return l;
 }
 
-// Fixed Hermite P(EC)^2 steps of S systems per workgroup for at most
-// P.quantum steps (Algorithm 1's loop, Algorithm 2's step).
-__global__ __launch_bounds__(kLargeMaxLanes) void k_plain_large(Bucket B, StepParams P, int S)
+// Evaluation state of one body in the step kernel's LDS (48 bytes, so a
+// partner is three ds_read_b128 at immediate offsets from one address).
+struct LargeBody {
+    double2 xy, zvx, vyvz;
+};
+
+// The step kernel's view of its dynamic LDS (E bodies): two copies of the
+// bodies' evaluation state, the masses and one int per body; the same bytes
+// as large_lds_bytes(E).
+struct LargeStepView {
+    LargeBody *st;   // copy c of body entry e at [c * E + e]
+    double *m;
+    int *flag;
+};
+
+__device__ __forceinline__ LargeStepView large_step_view(const int E)
 {
-    const int T = blockDim.x, n = B.n;
-    const LargeView V = large_view(T);
-    const LargeLane l = large_lane(B, S);
+    extern __shared__ char fb_dyn_lds[];
+    LargeStepView V;
+    V.st = reinterpret_cast<LargeBody *>(fb_dyn_lds);
+    V.m = reinterpret_cast<double *>(V.st + 2 * E);
+    V.flag = reinterpret_cast<int *>(V.m + E);
+    return V;
+}
+static_assert(2 * sizeof(LargeBody) + sizeof(double) + sizeof(int) ==
+                  6 * sizeof(double2) + sizeof(double) + sizeof(int),
+              "step-kernel LDS view must match large_lds_bytes");
+
+// Squared separations are floored here before the inverse distance is taken:
+// a body's interaction with itself (r = u = 0) then contributes exact zeros
+// with every intermediate finite, and no real pair comes this close.
+constexpr double kLargeMinR2 = 1e-100;
+
+// One interaction of body i with a partner (Eq. 1 and its time derivative,
+// the terms of bpl_interact).
+__device__ __forceinline__ void large_interact_p(const LargeBody &p, const double mj,
+                                                 const double (&xi)[3], const double (&vi)[3],
+                                                 double (&a)[3], double (&jk)[3])
+{
+    const double rx = p.xy.x - xi[0], ry = p.xy.y - xi[1], rz = p.zvx.x - xi[2];
+    const double ux = p.zvx.y - vi[0], uy = p.vyvz.x - vi[1], uz = p.vyvz.y - vi[2];
+    const double r2 = fmax(fma(rz, rz, fma(ry, ry, rx * rx)), kLargeMinR2);
+    const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
+    const double ri = rsqrt_nr(r2);
+    const double ri2 = ri * ri;
+    const double mr3 = mj * (ri2 * ri);
+    const double al = 3.0 * ru * ri2;
+    a[0] = fma(mr3, rx, a[0]);
+    a[1] = fma(mr3, ry, a[1]);
+    a[2] = fma(mr3, rz, a[2]);
+    jk[0] = fma(mr3, fma(-al, rx, ux), jk[0]);
+    jk[1] = fma(mr3, fma(-al, ry, uy), jk[1]);
+    jk[2] = fma(mr3, fma(-al, rz, uz), jk[2]);
+}
+
+// Waves per SIMD the register allocator targets for the large-n step kernel.
+#ifndef FB_LARGE_WAVES
+#define FB_LARGE_WAVES 2
+#endif
+
+// The evaluation of the K-body step kernel: publish this lane's bodies in
+// copy `cp` (entry system base + body), wait for the workgroup, then sum
+// each owned body's interactions: planets 1..n-1 in ascending order (its own
+// index contributing zeros), then the star.
+template <int K>
+__device__ __forceinline__ void large_eval_k(const LargeStepView &V, const int E, const int cp,
+                                             const int base, const int n, const bool live,
+                                             const int (&bk)[K], const bool (&own)[K],
+                                             const double (&xi)[K][3], const double (&vi)[K][3],
+                                             double (&a)[K][3], double (&jk)[K][3])
+{
+    LargeBody *st = V.st + cp * E + base;
+    const double *mm = V.m + base;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (own[k]) {
+            LargeBody &q = st[bk[k]];
+            q.xy = make_double2(xi[k][0], xi[k][1]);
+            q.zvx = make_double2(xi[k][2], vi[k][0]);
+            q.vyvz = make_double2(vi[k][1], vi[k][2]);
+        }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a[k][c] = 0.0;
+            jk[k][c] = 0.0;
+        }
+    if (!live)
+        return;
+#pragma unroll 2
+    for (int j = 1; j < n; ++j) {
+        const LargeBody p = st[j];
+        const double mj = mm[j];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            large_interact_p(p, mj, xi[k], vi[k], a[k], jk[k]);
+    }
+    const LargeBody p = st[0];
+    const double m0 = mm[0];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        large_interact_p(p, m0, xi[k], vi[k], a[k], jk[k]);
+}
+
+// Fixed Hermite P(EC)^2 steps (Algorithm 1's loop, Algorithm 2's step) for
+// at most P.quantum steps.  Lane h of a system owns bodies h, h + H, ...,
+// h + (K-1) H with H = ceil(n / K); S = floor(T / H) systems per workgroup
+// of T lanes.  The LDS arrays hold K T bodies, system s's at s n + body.
+// Every lane commits every iteration (so the pre-step state need not stay
+// live through the evaluations); a system's state is written back as soon
+// as it stops stepping, and its registers are ignored after that.
+template <int K>
+__global__ __launch_bounds__(kLargeMaxLanes / K) __attribute__((amdgpu_waves_per_eu(FB_LARGE_WAVES)))
+void k_plain_large(Bucket B, StepParams P, int S)
+{
+    const int T = blockDim.x, n = B.n, H = (n + K - 1) / K, E = K * T;
+    const LargeStepView V = large_step_view(E);
+    const int tid = threadIdx.x;
+    const int sys = tid / H, h = tid - sys * H;
+    const int slot0 = blockIdx.x * S + sys;
+    const bool valid = sys < S && slot0 < B.count;
+    const int slot = valid ? slot0 : 0;
+    const int base = sys * n;
     const size_t pitch = B.pitch;
-    double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
-    double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
-    Clock c;
-    c.status = ST_DONE;
-    if (l.valid) {
-        mi = B.st[(R_M * n + l.b) * pitch + l.slot];
+    int bk[K];
+    bool own[K];
+    double x[K][3], v[K][3], a0[K][3], j0[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        bk[k] = h + k * H;
+        own[k] = valid && bk[k] < n;
+        const int b = own[k] ? bk[k] : 0;
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-            x[cc] = B.st[((R_X + cc) * n + l.b) * pitch + l.slot];
-            v[cc] = B.st[((R_V + cc) * n + l.b) * pitch + l.slot];
-            a0[cc] = B.st[((R_A + cc) * n + l.b) * pitch + l.slot];
-            j0[cc] = B.st[((R_J + cc) * n + l.b) * pitch + l.slot];
+            x[k][cc] = v[k][cc] = a0[k][cc] = j0[k][cc] = 0.0;
+            if (own[k]) {
+                x[k][cc] = B.st[((R_X + cc) * n + b) * pitch + slot];
+                v[k][cc] = B.st[((R_V + cc) * n + b) * pitch + slot];
+                a0[k][cc] = B.st[((R_A + cc) * n + b) * pitch + slot];
+                j0[k][cc] = B.st[((R_J + cc) * n + b) * pitch + slot];
+            }
         }
-        c = load_clock(B, l.slot);
+        if (own[k])   // ordered before any read by the loop's first barrier
+            V.m[base + b] = B.st[(R_M * n + b) * pitch + slot];
     }
-    V.m[l.tid] = mi;   // ordered before any read by the loop's first barrier
-    for (int q = 0; q < P.quantum; ++q) {
-        double h = 0.0;
-        bool last = false;
-        const bool act = l.valid && plan_step(c, P, h, last);
-        if (!__syncthreads_or(act))
-            break;
-        const Coef k = make_coef(h);
-        double xc[3], vc[3], bx[3], bv[3], ak[3], jk[3];
+    Clock c;
+    c.status = ST_DONE;
+    if (valid)
+        c = load_clock(B, slot);
+    bool pending = false;   // registers hold committed steps not yet written back
+    int bad = 0;            // non-finite state written back
+    auto write_back = [&]() {
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-            predict_comp(k, x[cc], v[cc], a0[cc], j0[cc], xc[cc], vc[cc], bx[cc], bv[cc]);
-        large_eval(V, T, 0, l.tid, l.base, l.b, n, l.valid, xc, vc, ak, jk);
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-            correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
-        large_eval(V, T, 1, l.tid, l.base, l.b, n, l.valid, xc, vc, ak, jk);
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-            correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
-        if (act) {
+        for (int k = 0; k < K; ++k) {
+            if (!own[k])
+                continue;
+            const int b = bk[k];
+            bad |= (finite3(x[k]) && finite3(v[k])) ? 0 : 1;
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                x[cc] = xc[cc];
-                v[cc] = vc[cc];
-                a0[cc] = ak[cc];
-                j0[cc] = jk[cc];
+                B.st[((R_X + cc) * n + b) * pitch + slot] = x[k][cc];
+                B.st[((R_V + cc) * n + b) * pitch + slot] = v[k][cc];
+                B.st[((R_A + cc) * n + b) * pitch + slot] = a0[k][cc];
+                B.st[((R_J + cc) * n + b) * pitch + slot] = j0[k][cc];
             }
-            finish_step(c, P, last, h, 0.0);
+        }
+        pending = false;
+    };
+    for (int q = 0; q < P.quantum; ++q) {
+        double hs = 0.0;
+        bool last = false;
+        const bool act = valid && plan_step(c, P, hs, last);
+        if (pending && !act)
+            write_back();
+        if (!__syncthreads_or(act))
+            break;
+        const Coef cf = make_coef(hs);
+        double xc[K][3], vc[K][3], bx[K][3], bv[K][3], ak[K][3], jk[K][3];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+                predict_comp(cf, x[k][cc], v[k][cc], a0[k][cc], j0[k][cc], xc[k][cc], vc[k][cc],
+                             bx[k][cc], bv[k][cc]);
+        large_eval_k<K>(V, E, 0, base, n, act, bk, own, xc, vc, ak, jk);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+                correct_comp(cf, bx[k][cc], bv[k][cc], ak[k][cc], jk[k][cc], xc[k][cc], vc[k][cc]);
+        large_eval_k<K>(V, E, 1, base, n, act, bk, own, xc, vc, ak, jk);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                correct_comp(cf, bx[k][cc], bv[k][cc], ak[k][cc], jk[k][cc], x[k][cc], v[k][cc]);
+                a0[k][cc] = ak[k][cc];
+                j0[k][cc] = jk[k][cc];
+            }
+        if (act) {
+            finish_step(c, P, last, hs, 0.0);
+            pending = true;
         }
     }
-    V.flag[l.tid] = (l.valid && !(finite3(x) && finite3(v))) ? 1 : 0;
-    __syncthreads();
-    if (!l.valid)
-        return;
+    if (pending)
+        write_back();
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-        B.st[((R_X + cc) * n + l.b) * pitch + l.slot] = x[cc];
-        B.st[((R_V + cc) * n + l.b) * pitch + l.slot] = v[cc];
-        B.st[((R_A + cc) * n + l.b) * pitch + l.slot] = a0[cc];
-        B.st[((R_J + cc) * n + l.b) * pitch + l.slot] = j0[cc];
-    }
-    if (l.b == 0) {
+    for (int k = 0; k < K; ++k)
+        if (own[k])
+            V.flag[base + bk[k]] = bad;
+    __syncthreads();
+    if (valid && h == 0) {   // the lane of the star
         int fl = 0;
-        for (int k = 0; k < n; ++k)
-            fl |= V.flag[l.base + k];
+        for (int b = 0; b < n; ++b)
+            fl |= V.flag[base + b];
         if (fl)
             c.status = ST_NONFINITE;
-        store_clock(B, l.slot, c);
+        store_clock(B, slot, c);
     }
 }
 
@@ -2374,18 +2522,21 @@ hipError_t launch_pack(const Bucket &B, const double *mass, const double *pos,
     return hipGetLastError();
 }
 
-void large_shape(int n, int &T, int &S)
+void large_shape(int n, int k, int &T, int &S)
 {
     T = 0;
     S = 0;
+    if (k < 1)
+        return;
+    const int H = (n + k - 1) / k;   // lanes per system
     long long best_used = -1, best_T = 1;
-    for (int t = 64; t <= kLargeMaxLanes; t += 64) {
-        const int s = t / n;
+    for (int t = 64; t <= kLargeMaxLanes / k; t += 64) {
+        const int s = t / H;
         if (s < 1)
             continue;
-        // more of the lanes in use (s n / t), compared exactly; ties keep the smaller t
-        if ((long long)s * n * best_T > best_used * t) {
-            best_used = (long long)s * n;
+        // more of the lanes in use (s H / t), compared exactly; ties keep the smaller t
+        if ((long long)s * H * best_T > best_used * t) {
+            best_used = (long long)s * H;
             best_T = t;
             T = t;
             S = s;
@@ -2393,11 +2544,28 @@ void large_shape(int n, int &T, int &S)
     }
 }
 
-namespace {
-// Launch geometry of a large-n bucket: grid, lanes, systems per workgroup.
-bool large_launch(const Bucket &B, dim3 &grid, int &T, int &S)
+int large_bodies_per_lane(int n)
 {
-    large_shape(B.n, T, S);
+    // Two bodies per lane halve the LDS reads per interaction; one is kept
+    // where pairing would idle clearly more body slots (odd n with few
+    // systems per workgroup).
+    int T1, S1, T2, S2;
+    large_shape(n, 1, T1, S1);
+    large_shape(n, 2, T2, S2);
+    if (S2 < 1)
+        return 1;
+    if (S1 < 1)
+        return 2;
+    const double use1 = (double)S1 * n / T1, use2 = (double)S2 * n / (2.0 * T2);
+    return use2 >= use1 - 0.02 ? 2 : 1;
+}
+
+namespace {
+// Launch geometry of a large-n bucket with k bodies per lane: grid, lanes,
+// systems per workgroup.
+bool large_launch(const Bucket &B, int k, dim3 &grid, int &T, int &S)
+{
+    large_shape(B.n, k, T, S);
     if (S < 1)
         return false;
     grid = dim3((unsigned)((B.count + S - 1) / S));
@@ -2412,7 +2580,7 @@ hipError_t launch_prepare(const Bucket &B, hipStream_t s)
     if (B.n > kMaxBodies) {
         dim3 grid;
         int T, S;
-        if (!large_launch(B, grid, T, S))
+        if (!large_launch(B, 1, grid, T, S))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_prepare_large, grid, dim3(T), large_lds_bytes(T), s, B, S);
         return hipGetLastError();
@@ -2453,9 +2621,13 @@ hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const
     if (B.n > kMaxBodies) {
         dim3 grid;
         int T, S;
-        if (adv || !large_launch(B, grid, T, S))
+        const int K = large_bodies_per_lane(B.n);
+        if (adv || !large_launch(B, K, grid, T, S))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_plain_large, grid, dim3(T), large_lds_bytes(T), s, B, P, S);
+        if (K == 2)
+            hipLaunchKernelGGL(k_plain_large<2>, grid, dim3(T), large_lds_bytes(2 * T), s, B, P, S);
+        else
+            hipLaunchKernelGGL(k_plain_large<1>, grid, dim3(T), large_lds_bytes(T), s, B, P, S);
         return hipGetLastError();
     }
     if (mapping == MAP_SPL && B.n <= (adv ? kMaxSplAdv : kMaxSplBodies)) {
@@ -2592,7 +2764,7 @@ hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs
     if (B.n > kMaxBodies) {
         dim3 grid;
         int T, S;
-        if (mvs_form || !large_launch(B, grid, T, S))
+        if (mvs_form || !large_launch(B, 1, grid, T, S))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_diag_large, grid, dim3(T), large_lds_bytes(T), s, B, S, energy,
                            angmom);
@@ -2682,7 +2854,7 @@ hipError_t launch_log(const Bucket &B, const long long *orig_off, int kind, cons
     if (B.n > kMaxBodies) {
         dim3 grid;
         int T, S;
-        if (!large_launch(B, grid, T, S))
+        if (!large_launch(B, 1, grid, T, S))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_log_large, grid, dim3(T), large_lds_bytes(T), s, B, S, orig_off,
                            kind, los[0], los[1], los[2], k, max_records, out);
