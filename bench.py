@@ -46,7 +46,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 # FETCH_SIZE / WRITE_SIZE counter passes (scaled by a 256 MiB copy kernel's
 # reading) recorded in profiles/, keyed by the kernel source they measured.
 MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1,
-                    "1c9dff3d544099cf": 92417308.4, "234f298587126ea3": 92405022.4}
+                    "1c9dff3d544099cf": 92417308.4, "234f298587126ea3": 92405022.4,
+                    "b0cf1370d8600140": 92417213.2}
 # Hardware counters of the same kernel on this workload (profiles/), keyed the
 # same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
 # lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
@@ -56,6 +57,8 @@ MEASURED_COUNTERS = {
                          "shader_clock_ghz": 2.018, "valu_insts_per_system_step": 388.01},
     "234f298587126ea3": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9753,
                          "shader_clock_ghz": 1.996, "valu_insts_per_system_step": 388.01},
+    "b0cf1370d8600140": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9729,
+                         "shader_clock_ghz": 1.977, "valu_insts_per_system_step": 388.01},
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
@@ -262,6 +265,28 @@ def rkck_extras(fb, gen, torch, log, steps=2000):
     return out
 
 
+def large_n_extras(fb, gen, torch, log):
+    """The large-n gravitation (systems of 17..512 bodies, Section 4.2's
+    second variant): fixed Hermite steps (dt 2pi/1000) on planetesimal disks.
+    Algorithmic FP64 work counts each pair once per evaluation (the kernel
+    evaluates every pair from both sides, twice that)."""
+    out = {}
+    for name, steps in (("disk_16384x17", 20000), ("disk_4096x64", 5000), ("disk_2048x128", 2000),
+                        ("disk_512x512", 500)):
+        ens, p = gen.workload(name)
+        n = int(ens.n_body[0])
+        timed(fb, torch, ens.subset(range(64)), lambda E: E.integrate_steps(2, p["dt"]))   # code load
+        t, st = timed(fb, torch, ens, lambda E: E.integrate_steps(steps, p["dt"]))
+        assert (st["status"] == fb.DONE).all()
+        sps = ens.n_sys * steps / t
+        alg = sps * flops_per_system_step(n) / 1e12
+        out[name] = {"steps": steps, "seconds": t, "system_steps_per_s": sps,
+                     "pair_interactions_per_s": sps * 2 * n * (n - 1) / 2,
+                     "fp64_tflops_algorithmic": alg, "frac_fp64_peak": alg / FP64_VECTOR_PEAK_TFLOPS}
+        log(f"[bench] large-n {name}: {sps:.3e} system-steps/s, {alg:.1f} TFLOP/s algorithmic")
+    return out
+
+
 def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, policy="srpt",
                    cls="spl", quantum_tiles=0, long_steps=300000):
     from paper_1208_1157_amd import serve
@@ -434,6 +459,7 @@ def main():
         extras["paper_ics"] = paper_ic_extras(fb, gen, torch, log)
         extras["mvs"] = mvs_extras(fb, gen, torch, log)
         extras["rkck"] = rkck_extras(fb, gen, torch, log)
+        extras["large_n"] = large_n_extras(fb, gen, torch, log)
     if extras:
         result["extras"] = extras
     if not args.no_cpu:
