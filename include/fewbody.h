@@ -220,6 +220,21 @@ fb_status fb_integrate_steps_logged(fb_ensemble *e, int64_t n_steps, double dt,
                                     const fb_opts *o, const fb_log_spec *log,
                                     int32_t *n_records);
 
+/* Integration to observation times with the monitor of `log` (Section 4.3's
+ * logging at the caller's times; with FB_LOG_RV, Section 4.4's radial
+ * velocity reduction at each epoch).  For k = 0 .. n_times-1 in turn, every
+ * system integrates to t_obs[k] with the semantics of fb_integrate (fixed dt
+ * > 0 with the last step shortened, or adaptive steps; stop rules; either
+ * schedule), then record k is written.  A system stopped by a rule, or
+ * already at or past t_obs[k], keeps its state: its record's t says where it
+ * is.  Because each run lands on its time, the step before each time is
+ * shortened, so the trajectory differs from one run straight to the last
+ * time.  t_obs is a host array, finite and strictly increasing; log.every
+ * is ignored; log.max_records must be >= n_times.  *n_records (may be NULL)
+ * gets the records written. */
+fb_status fb_integrate_to_times(fb_ensemble *e, int32_t n_times, const double *t_obs, double dt,
+                                const fb_opts *o, const fb_log_spec *log, int32_t *n_records);
+
 /* Runge-Kutta Cash-Karp integration (Sections 2.2.2 and 4.3.2): the embedded
  * 4(5) pair of Cash & Karp (1990) on (x, v) with accelerations from Eq. 1,
  * six acceleration evaluations per step or trial step, one body per lane,

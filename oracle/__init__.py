@@ -179,21 +179,30 @@ def paper_timestep(acc, jerk, tau):
 
 
 def integrate_adaptive(mass, pos, vel, t_end, eta=0.01, stop_rules=3, r_eject=100.0,
-                       max_steps=10**9, t0=0.0, paper_rule=False):
+                       max_steps=10**9, t0=0.0, paper_rule=False, acc=None, jerk=None,
+                       dt_next=None, steps=0):
     """Adaptive integration of one system to t_end or a stop rule.
 
-    paper_rule selects Eq. 5 (eta is tau) instead of the pairwise rule.
+    paper_rule selects Eq. 5 (eta is tau) instead of the pairwise rule.  With
+    acc, jerk and dt_next given (a previous call's results) the run continues
+    from them instead of the set-up evaluation; steps counts on from `steps`.
     Returns dict(pos, vel, acc, jerk, t, dt_next, steps, status)."""
     m = _f64(mass)
     n = m.shape[0]
     x, v = _f64(pos, (n, 3)).copy(), _f64(vel, (n, 3)).copy()
-    a, j = np.zeros((n, 3)), np.zeros((n, 3))
+    flags = 2 if paper_rule else 0
+    if acc is None or jerk is None or dt_next is None:
+        a, j = np.zeros((n, 3)), np.zeros((n, 3))
+        dtn = np.zeros(1)
+        flags |= 1
+    else:
+        a, j = _f64(acc, (n, 3)).copy(), _f64(jerk, (n, 3)).copy()
+        dtn = np.array([dt_next], dtype=np.float64)
     t = np.array([t0], dtype=np.float64)
-    dtn = np.zeros(1)
-    steps = np.zeros(1, dtype=np.int64)
+    steps = np.array([steps], dtype=np.int64)
     st = lib().ora_integrate_adaptive(n, _p(m), _p(x), _p(v), _p(a), _p(j), _p(t), float(t_end),
                                       float(eta), int(stop_rules), float(r_eject), int(max_steps),
-                                      _p(dtn), _p(steps), 1 | (2 if paper_rule else 0))
+                                      _p(dtn), _p(steps), flags)
     return {"pos": x, "vel": v, "acc": a, "jerk": j, "t": float(t[0]), "dt_next": float(dtn[0]),
             "steps": int(steps[0]), "status": int(st)}
 

@@ -675,6 +675,36 @@ fb_status run_mvs(fb_ensemble *e, const fb_opts &o, long long step_bound)
     }
 }
 
+// A log spec for a run that writes `records` records: kind, capacity, buffer
+// size and (FB_LOG_RV) the line of sight, returned normalised in los.
+fb_status check_log(const fb_ensemble *e, const fb_log_spec *log, long long records,
+                    double (&los)[3])
+{
+    if (log->max_records < 1)
+        return fail(FB_E_INVAL, "log.max_records must be >= 1");
+    if (records > log->max_records)
+        return fail(FB_E_INVAL, "the run makes %lld records, log.max_records is %d", records,
+                    log->max_records);
+    if (log->kind != FB_LOG_STATE && log->kind != FB_LOG_RV && log->kind != FB_LOG_ENERGY)
+        return fail(FB_E_INVAL, "unknown log kind %d", log->kind);
+    const size_t need = fb_log_bytes(e->n_sys, e->n_body.data(), log->kind, log->max_records);
+    if (e->n_sys > 0 && (!log->d_buffer || log->buffer_bytes < need))
+        return fail(FB_E_INVAL, "log buffer of %zu bytes, %zu needed", log->buffer_bytes, need);
+    los[0] = 0.0;
+    los[1] = 0.0;
+    los[2] = 1.0;
+    if (log->kind == FB_LOG_RV) {
+        const double l2 = log->los[0] * log->los[0] + log->los[1] * log->los[1] +
+                          log->los[2] * log->los[2];
+        if (!(std::isfinite(l2) && l2 > 0.0))
+            return fail(FB_E_INVAL, "log.los must be a finite non-zero vector");
+        const double inv = 1.0 / std::sqrt(l2);
+        for (int c = 0; c < 3; ++c)
+            los[c] = log->los[c] * inv;
+    }
+    return FB_OK;
+}
+
 fb_status run(fb_ensemble *e, const fb_opts &o, long long step_bound)
 {
     if (o.schedule == FB_SCHED_PERSISTENT)
@@ -915,27 +945,13 @@ fb_status fb_integrate_steps_logged(fb_ensemble *e, int64_t n_steps, double dt, 
         return st;
     if (n_steps < 0 || !(std::isfinite(dt) && dt != 0.0))
         return fail(FB_E_INVAL, "n_steps must be >= 0 and dt finite and non-zero");
-    if (log->every < 1 || log->max_records < 1)
-        return fail(FB_E_INVAL, "log.every and log.max_records must be >= 1");
+    if (log->every < 1)
+        return fail(FB_E_INVAL, "log.every must be >= 1");
     const long long records = 1 + n_steps / log->every + (n_steps % log->every ? 1 : 0);
-    if (records > log->max_records)
-        return fail(FB_E_INVAL, "the run makes %lld records, log.max_records is %d", records,
-                    log->max_records);
-    const size_t need = fb_log_bytes(e->n_sys, e->n_body.data(), log->kind, log->max_records);
-    if (need == 0 && e->n_sys > 0)
-        return fail(FB_E_INVAL, "unknown log kind %d", log->kind);
-    if (!log->d_buffer || log->buffer_bytes < need)
-        return fail(FB_E_INVAL, "log buffer of %zu bytes, %zu needed", log->buffer_bytes, need);
-    double los[3] = {0.0, 0.0, 1.0};
-    if (log->kind == FB_LOG_RV) {
-        const double l2 = log->los[0] * log->los[0] + log->los[1] * log->los[1] +
-                          log->los[2] * log->los[2];
-        if (!(std::isfinite(l2) && l2 > 0.0))
-            return fail(FB_E_INVAL, "log.los must be a finite non-zero vector");
-        const double inv = 1.0 / std::sqrt(l2);
-        for (int c = 0; c < 3; ++c)
-            los[c] = log->los[c] * inv;
-    }
+    double los[3];
+    st = check_log(e, log, records, los);
+    if (st != FB_OK)
+        return st;
     if (e->n_sys == 0)
         return FB_OK;
     st = ensure_inertial(e);
@@ -963,6 +979,56 @@ fb_status fb_integrate_steps_logged(fb_ensemble *e, int64_t n_steps, double dt, 
     }
     if (n_records)
         *n_records = k;
+    return FB_OK;
+}
+
+fb_status fb_integrate_to_times(fb_ensemble *e, int32_t n_times, const double *t_obs, double dt,
+                                const fb_opts *po, const fb_log_spec *log, int32_t *n_records)
+{
+    if (!e || !log || !t_obs)
+        return fail(FB_E_INVAL, "ensemble, times and log are required");
+    if (n_records)
+        *n_records = 0;
+    fb_opts o;
+    fb_opts_default(&o);
+    if (po)
+        o = *po;
+    fb_status st = check_opts(o);
+    if (st != FB_OK)
+        return st;
+    st = check_large(e, o);
+    if (st != FB_OK)
+        return st;
+    if (!o.adaptive && !(std::isfinite(dt) && dt > 0.0))
+        return fail(FB_E_INVAL, "dt must be finite and > 0 (the times increase)");
+    if (n_times < 1)
+        return fail(FB_E_INVAL, "n_times must be >= 1");
+    for (int32_t k = 0; k < n_times; ++k)
+        if (!std::isfinite(t_obs[k]) || (k > 0 && !(t_obs[k] > t_obs[k - 1])))
+            return fail(FB_E_INVAL, "times must be finite and strictly increasing (index %d)", k);
+    double los[3];
+    st = check_log(e, log, n_times, los);
+    if (st != FB_OK)
+        return st;
+    if (e->n_sys == 0)
+        return FB_OK;
+    st = ensure_inertial(e);
+    if (st != FB_OK)
+        return st;
+    double *out = static_cast<double *>(log->d_buffer);
+    const int rule = o.adaptive == 2 ? 2 : (o.adaptive ? 1 : 0);
+    for (int32_t k = 0; k < n_times; ++k) {
+        for (const Bucket &B : e->buckets)
+            FB_HIP(launch_begin_run(B, 0, 0, t_obs[k], dt, rule, o.eta, e->stream));
+        st = run(e, o, -1);
+        if (st != FB_OK)
+            return st;
+        for (const Bucket &B : e->buckets)
+            FB_HIP(launch_log(B, e->d_orig_off, log->kind, los, k, log->max_records, out,
+                              e->stream));
+    }
+    if (n_records)
+        *n_records = n_times;
     return FB_OK;
 }
 

@@ -90,6 +90,8 @@ _SIGS = {
     "fb_log_bytes": (_sz, [_i32, _p, _i32, _i32]),
     "fb_integrate_steps_logged": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts),
                                                  ctypes.POINTER(FbLogSpec), _p]),
+    "fb_integrate_to_times": (ctypes.c_int, [_p, _i32, _p, _d, ctypes.POINTER(FbOpts),
+                                             ctypes.POINTER(FbLogSpec), _p]),
     "fb_integrate_rkck_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate_rkck": (ctypes.c_int, [_p, _d, _d, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate": (ctypes.c_int, [_p, _d, _d, ctypes.POINTER(FbOpts)]),
@@ -274,29 +276,52 @@ class Ensemble:
         if every < 1:
             raise FewbodyError(E_INVAL, "every must be >= 1")
         R = max_records or (1 + n_steps // every + (1 if n_steps % every else 0))
-        torch = self._torch
-        nb = self.n_body
-        nbytes = int(_lib.fb_log_bytes(int(nb.shape[0]), _ptr(nb), int(kind), int(R)))
-        if nbytes == 0:
-            raise FewbodyError(E_INVAL, "invalid log kind or record count")
-        with torch.cuda.stream(self.stream):
-            buf = torch.empty(nbytes, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
-        spec = FbLogSpec(int(kind), int(every), int(R), 0, (ctypes.c_double * 3)(*los),
-                         ctypes.c_void_p(buf.data_ptr()), nbytes)
+        buf, spec = self._log_buffer(kind, R, los, every)
         o = (opts or Opts()).c()
         n_rec = ctypes.c_int32()
         _check(_lib.fb_integrate_steps_logged(self._handle, int(n_steps), float(dt), ctypes.byref(o),
                                               ctypes.byref(spec), ctypes.byref(n_rec)))
+        return self._read_log(buf, kind, R, n_rec.value)
+
+    def integrate_to_times(self, t_obs, dt=0.0, kind=LOG_RV, los=(0.0, 0.0, 1.0),
+                           opts: Opts | None = None):
+        """fb_integrate_to_times: integrate to each time of t_obs in turn and
+        record every system there; returns the records as
+        integrate_steps_logged does (R = len(t_obs))."""
+        t = np.ascontiguousarray(t_obs, dtype=np.float64).reshape(-1)
+        R = max(int(t.shape[0]), 1)
+        buf, spec = self._log_buffer(kind, R, los, 0)
+        o = (opts or Opts()).c()
+        n_rec = ctypes.c_int32()
+        _check(_lib.fb_integrate_to_times(self._handle, int(t.shape[0]), _ptr(t), float(dt), ctypes.byref(o),
+                                          ctypes.byref(spec), ctypes.byref(n_rec)))
+        return self._read_log(buf, kind, R, n_rec.value)
+
+    def _log_buffer(self, kind, R, los, every):
+        torch = self._torch
+        nb = self.n_body
+        nbytes = int(_lib.fb_log_bytes(int(nb.shape[0]), _ptr(nb), int(kind), int(R)))
+        if nbytes == 0 and self.n_sys > 0:
+            raise FewbodyError(E_INVAL, "invalid log kind or record count")
+        with torch.cuda.stream(self.stream):
+            buf = torch.empty(max(nbytes, 8), dtype=torch.uint8,
+                              device=torch.device("cuda", torch.cuda.current_device()))
+        spec = FbLogSpec(int(kind), int(every), int(R), 0, (ctypes.c_double * 3)(*los),
+                         ctypes.c_void_p(buf.data_ptr()), nbytes)
+        return buf, spec
+
+    def _read_log(self, buf, kind, R, k):
         self.synchronize()
+        nb = self.n_body
+        S = int(nb.shape[0])
         host = buf.cpu().numpy().view(np.float64)
-        k, S = n_rec.value, int(nb.shape[0])
         if kind == LOG_RV:
-            a = host.reshape(S, R, 2)[:, :k]
+            a = host[:S * R * 2].reshape(S, R, 2)[:, :k]
             return a[..., 0], a[..., 1]
         if kind == LOG_ENERGY:
-            a = host.reshape(S, R, 5)[:, :k]
+            a = host[:S * R * 5].reshape(S, R, 5)[:, :k]
             return a[..., 0], a[..., 1], a[..., 2:5]
-        off = np.concatenate([[0], np.cumsum(nb)])
+        off = np.concatenate([[0], np.cumsum(nb)]).astype(np.int64)
         N = int(off[-1])
         t = np.empty((S, k))
         pos = np.empty((k, N, 3))

@@ -1,7 +1,8 @@
 """The monitor and its log buffer (Section 4.3) with Section 4.4's data
 reduction, against the Hermite oracle: logged states, the star's radial
-velocity and the conserved quantities at every record; the logged run ends
-bitwise where the unlogged one does; argument checks."""
+velocity and the conserved quantities at every record, every k steps or at
+observation epochs (fixed and adaptive steps, both schedules); the logged
+run ends bitwise where the unlogged one does; argument checks."""
 import math
 import sys
 
@@ -154,4 +155,128 @@ def test_argument_checks(fb):
         assert ei.value.code == fb.E_INVAL
     st0 = E.state()
     assert np.all(st0["steps"] == 0)           # nothing ran
+    E.close()
+
+
+# ---- records at observation times (fb_integrate_to_times) -------------------
+
+def oracle_fixed_to_times(ora, m, x, v, dt, times):
+    """The oracle run to each time in turn with fb_integrate's fixed-step
+    rule: whole steps of dt while they stay short of the time, then one
+    shortened step onto it; (a0, j0) carried throughout."""
+    a = j = None
+    t = 0.0
+    out = []
+    for T in times:
+        nf = int(math.floor((T - t) / dt))
+        while nf > 0 and t + nf * dt > T:
+            nf -= 1
+        if nf > 0:
+            x, v, a, j = ora.integrate_fixed(m, x, v, dt, nf, acc=a, jerk=j)
+        rem = T - (t + nf * dt)
+        if rem > 1e-9 * dt:
+            x, v, a, j = ora.integrate_fixed(m, x, v, rem, 1, acc=a, jerk=j)
+        t = T
+        out.append((x, v))
+    return out
+
+
+def test_observation_times_fixed_dt(fb, ora):
+    """Radial velocities at uneven epochs (whole chunks of 23.55, 40.1, 95.5
+    and 0.64 steps) against the oracle run to each epoch."""
+    ens = ragged()
+    dt = TWO_PI / 400
+    times = [0.37, 1.0, 2.5, 2.51]
+    los = (0.2, 1.0, -0.4)
+    E = fb.from_gen(ens)
+    t, rv = E.integrate_to_times(times, dt, kind=fb.LOG_RV, los=los)
+    st = E.state()
+    E.close()
+    assert t.shape == (ens.n_sys, 4) and np.all(t == np.array(times)[None, :])
+    assert np.all(st["t"] == times[-1]) and np.all(st["status"] == fb.DONE)
+    lhat = np.array(los) / np.linalg.norm(los)
+    off = ens.offsets
+    for s in range(ens.n_sys):
+        m, x, v = ens.system(s)
+        for k, (xs, vs) in enumerate(oracle_fixed_to_times(ora, m, x, v, dt, times)):
+            want = (vs[0] - m @ vs / m.sum()) @ lhat
+            scale = np.linalg.norm(vs, axis=1).max()
+            assert abs(rv[s, k] - want) <= 2 * REL_TOL * scale, (s, k, rv[s, k], want)
+        if s == 0:
+            assert np.all(st["steps"][s] == 24 + 41 + 96 + 1)
+
+
+@pytest.mark.parametrize("rule", [1, 2])
+def test_observation_times_adaptive(fb, ora, rule):
+    """Adaptive steps (pairwise rule, or Eq. 5) to three epochs on both
+    schedules; states against the oracle chained with its carried (a0, j0)
+    and step, for the systems whose step counts agree."""
+    ens = gen.three_body(96, seed=63)
+    times = [1.3, 4.0, 6.2]
+    eta = 0.01 if rule == 1 else 1.7e-2
+    refs = []
+    for s in range(ens.n_sys):
+        m, x, v = ens.system(s)
+        a = j = dtn = None
+        tt, steps, recs = 0.0, 0, []
+        for T in times:
+            o = ora.integrate_adaptive(m, x, v, T, eta=eta, stop_rules=0, t0=tt, paper_rule=rule == 2,
+                                       acc=a, jerk=j, dt_next=dtn, steps=steps)
+            assert o["status"] == ora.DONE
+            x, v, a, j = o["pos"], o["vel"], o["acc"], o["jerk"]
+            dtn, tt, steps = o["dt_next"], o["t"], o["steps"]
+            recs.append((x, v))
+        refs.append((steps, recs))
+    off = ens.offsets
+    for sched in (fb.SCHED_PLAIN, fb.SCHED_PERSISTENT):
+        say("epochs adaptive", rule, sched)
+        E = fb.from_gen(ens)
+        t, pos, vel = E.integrate_to_times(times, kind=fb.LOG_STATE,
+                                           opts=fb.Opts(adaptive=rule, eta=eta, schedule=sched,
+                                                        steps_per_quantum=50))
+        st = E.state()
+        E.close()
+        assert np.all(t == np.array(times)[None, :]) and np.all(st["status"] == fb.DONE)
+        agree = 0
+        for s, (steps, recs) in enumerate(refs):
+            if steps != st["steps"][s]:
+                continue
+            agree += 1
+            sl = slice(off[s], off[s + 1])
+            for k, (xs, vs) in enumerate(recs):
+                assert per_system_rel_err([3], pos[k][sl], xs)[0] <= REL_TOL, (sched, s, k)
+                assert per_system_rel_err([3], vel[k][sl], vs)[0] <= REL_TOL, (sched, s, k)
+        assert agree >= 0.97 * ens.n_sys, (sched, agree)
+
+
+def test_observation_times_one_epoch_is_fb_integrate(fb):
+    ens = ragged()
+    dt = TWO_PI / 300
+    out = []
+    for logged in (False, True):
+        E = fb.from_gen(ens)
+        if logged:
+            E.integrate_to_times([3.3], dt, kind=fb.LOG_ENERGY)
+        else:
+            E.integrate(3.3, dt)
+        out.append(E.state())
+        E.close()
+    for key in ("pos", "vel", "t", "steps"):
+        assert np.array_equal(out[0][key], out[1][key]), key
+
+
+def test_observation_times_argument_checks(fb):
+    E = fb.from_gen(gen.three_body(8, seed=64))
+    bad = [lambda: E.integrate_to_times([1.0, 1.0], 0.01),
+           lambda: E.integrate_to_times([1.0, 0.5], 0.01),
+           lambda: E.integrate_to_times([1.0, float("nan")], 0.01),
+           lambda: E.integrate_to_times([], 0.01),
+           lambda: E.integrate_to_times([1.0], 0.0),
+           lambda: E.integrate_to_times([1.0], -0.01),
+           lambda: E.integrate_to_times([1.0], 0.01, kind=9)]
+    for f in bad:
+        with pytest.raises(fb.FewbodyError) as ei:
+            f()
+        assert ei.value.code == fb.E_INVAL
+    assert np.all(E.state()["steps"] == 0)
     E.close()
