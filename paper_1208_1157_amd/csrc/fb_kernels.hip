@@ -1222,14 +1222,6 @@ __global__ void k_begin_run(Bucket B, int fixed_steps, long long n_steps, double
     }
 }
 
-// Run start of a large-n bucket (fixed steps only).
-__global__ void k_begin_run_large(Bucket B, int fixed_steps, long long n_steps, double t_end,
-                                  double dt)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < B.count)
-        (void)begin_run_clock(B, s, fixed_steps, n_steps, t_end, dt, 0);
-}
 
 // bucket SoA -> AoS rows in caller order (any output may be null).
 __global__ void k_unpack(Bucket B, const long long *__restrict__ orig_off, double *pos,
@@ -1962,17 +1954,18 @@ void k_plain_rkck(Bucket B, StepParams P, double eps)
 // Lanes of the largest large-n workgroup (its LDS stays below 64 KiB).
 constexpr int kLargeMaxLanes = 512;
 
-// Dynamic LDS of a large-n workgroup of T lanes: two copies of the
-// evaluation state (three 16-byte pairs per lane each), the masses and one
-// int per lane.
+// Dynamic LDS of a large-n workgroup holding T bodies: two copies of the
+// evaluation state (three 16-byte pairs per body each), the masses, one
+// reduction double and one int per body.
 __host__ __device__ constexpr size_t large_lds_bytes(int T)
 {
-    return (size_t)T * (6 * sizeof(double2) + sizeof(double) + sizeof(int));
+    return (size_t)T * (6 * sizeof(double2) + 2 * sizeof(double) + sizeof(int));
 }
 
 struct LargeView {
     double2 *xy, *zvx, *vyvz;   // copy c of lane l at [c * T + l]
     double *m;
+    double *red;
     int *flag;
 };
 
@@ -1985,7 +1978,8 @@ __device__ __forceinline__ LargeView large_view(const int T)
     V.zvx = p + 2 * T;
     V.vyvz = p + 4 * T;
     V.m = reinterpret_cast<double *>(p + 6 * T);
-    V.flag = reinterpret_cast<int *>(V.m + T);
+    V.red = V.m + T;
+    V.flag = reinterpret_cast<int *>(V.red + T);
     return V;
 }
 
@@ -2081,6 +2075,7 @@ struct LargeBody {
 struct LargeStepView {
     LargeBody *st;   // copy c of body entry e at [c * E + e]
     double *m;
+    double *red;
     int *flag;
 };
 
@@ -2090,11 +2085,12 @@ __device__ __forceinline__ LargeStepView large_step_view(const int E)
     LargeStepView V;
     V.st = reinterpret_cast<LargeBody *>(fb_dyn_lds);
     V.m = reinterpret_cast<double *>(V.st + 2 * E);
-    V.flag = reinterpret_cast<int *>(V.m + E);
+    V.red = V.m + E;
+    V.flag = reinterpret_cast<int *>(V.red + E);
     return V;
 }
-static_assert(2 * sizeof(LargeBody) + sizeof(double) + sizeof(int) ==
-                  6 * sizeof(double2) + sizeof(double) + sizeof(int),
+static_assert(2 * sizeof(LargeBody) + 2 * sizeof(double) + sizeof(int) ==
+                  6 * sizeof(double2) + 2 * sizeof(double) + sizeof(int),
               "step-kernel LDS view must match large_lds_bytes");
 
 // Squared separations are floored here before the inverse distance is taken:
@@ -2103,10 +2099,12 @@ static_assert(2 * sizeof(LargeBody) + sizeof(double) + sizeof(int) ==
 constexpr double kLargeMinR2 = 1e-100;
 
 // One interaction of body i with a partner (Eq. 1 and its time derivative,
-// the terms of bpl_interact).
+// the terms of bpl_interact).  With TS, also the pair's step-rule quantity
+// (|u|^2 + 3 (r.u)^2/|r|^2) / |r|^2 into wmax (zero for the self term).
+template <bool TS>
 __device__ __forceinline__ void large_interact_p(const LargeBody &p, const double mj,
                                                  const double (&xi)[3], const double (&vi)[3],
-                                                 double (&a)[3], double (&jk)[3])
+                                                 double (&a)[3], double (&jk)[3], double &wmax)
 {
     const double rx = p.xy.x - xi[0], ry = p.xy.y - xi[1], rz = p.zvx.x - xi[2];
     const double ux = p.zvx.y - vi[0], uy = p.vyvz.x - vi[1], uz = p.vyvz.y - vi[2];
@@ -2122,6 +2120,10 @@ __device__ __forceinline__ void large_interact_p(const LargeBody &p, const doubl
     jk[0] = fma(mr3, fma(-al, rx, ux), jk[0]);
     jk[1] = fma(mr3, fma(-al, ry, uy), jk[1]);
     jk[2] = fma(mr3, fma(-al, rz, uz), jk[2]);
+    if (TS) {
+        const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+        wmax = fmax(wmax, fma(al, ru, u2) * ri2);
+    }
 }
 
 // Waves per SIMD the register allocator targets for the large-n step kernel.
@@ -2133,12 +2135,13 @@ __device__ __forceinline__ void large_interact_p(const LargeBody &p, const doubl
 // copy `cp` (entry system base + body), wait for the workgroup, then sum
 // each owned body's interactions: planets 1..n-1 in ascending order (its own
 // index contributing zeros), then the star.
-template <int K>
+template <int K, bool TS>
 __device__ __forceinline__ void large_eval_k(const LargeStepView &V, const int E, const int cp,
                                              const int base, const int n, const bool live,
                                              const int (&bk)[K], const bool (&own)[K],
                                              const double (&xi)[K][3], const double (&vi)[K][3],
-                                             double (&a)[K][3], double (&jk)[K][3])
+                                             double (&a)[K][3], double (&jk)[K][3],
+                                             double (&w)[K])
 {
     LargeBody *st = V.st + cp * E + base;
     const double *mm = V.m + base;
@@ -2152,12 +2155,14 @@ __device__ __forceinline__ void large_eval_k(const LargeStepView &V, const int E
         }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+        w[k] = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             a[k][c] = 0.0;
             jk[k][c] = 0.0;
         }
+    }
     if (!live)
         return;
 #pragma unroll 2
@@ -2166,13 +2171,102 @@ __device__ __forceinline__ void large_eval_k(const LargeStepView &V, const int E
         const double mj = mm[j];
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            large_interact_p(p, mj, xi[k], vi[k], a[k], jk[k]);
+            large_interact_p<TS>(p, mj, xi[k], vi[k], a[k], jk[k], w[k]);
     }
     const LargeBody p = st[0];
     const double m0 = mm[0];
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        large_interact_p(p, m0, xi[k], vi[k], a[k], jk[k]);
+        large_interact_p<TS>(p, m0, xi[k], vi[k], a[k], jk[k], w[k]);
+}
+
+// Per-system reduction of one value per owned body, in body order (max, or
+// sum); every valid lane gets its system's result.  Two barriers.
+template <int K, bool MAXOP>
+__device__ __forceinline__ double large_sys_reduce(double *red, const int base, const int n,
+                                                   const bool valid, const int (&bk)[K],
+                                                   const bool (&own)[K], const double (&val)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (own[k])
+            red[base + bk[k]] = val[k];
+    __syncthreads();
+    double r = 0.0;
+    if (valid) {
+        r = red[base];
+        for (int b = 1; b < n; ++b)
+            r = MAXOP ? fmax(r, red[base + b]) : r + red[base + b];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Stop-rule flags of each system after a committed step (the bits of
+// bpl_stop_flags: 1 non-finite, 2 two planets within one mutual Hill radius,
+// 4 a planet beyond r_eject), OR-ed over the system; positions go through
+// copy 0 of the evaluation state, free until the next step's first
+// evaluation.
+template <int K>
+__device__ __forceinline__ int large_stop_flags(const LargeStepView &V, const int base,
+                                                const int n, const bool valid, const int (&bk)[K],
+                                                const bool (&own)[K], const double (&x)[K][3],
+                                                const double (&v)[K][3], const StepParams &P)
+{
+    int fl = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (own[k]) {
+            fl |= (finite3(x[k]) && finite3(v[k])) ? 0 : 1;
+            V.st[base + bk[k]].xy = make_double2(x[k][0], x[k][1]);
+            V.st[base + bk[k]].zvx.x = x[k][2];
+        }
+    __syncthreads();
+    double rb[K];
+    if (valid) {
+        const LargeBody s0 = V.st[base];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double dx = x[k][0] - s0.xy.x, dy = x[k][1] - s0.xy.y, dz = x[k][2] - s0.zvx.x;
+            rb[k] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+            if (own[k])
+                V.red[base + bk[k]] = rb[k];
+        }
+    }
+    __syncthreads();
+    if (valid) {
+        const double inv24m0 = 1.0 / (24.0 * V.m[base]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!own[k] || bk[k] == 0)
+                continue;
+            if ((P.stop_rules & 2) && rb[k] > P.r_eject)
+                fl |= 4;
+            if (P.stop_rules & 1) {
+                const double mi = V.m[base + bk[k]];
+                for (int j = 1; j < n; ++j) {
+                    if (j == bk[k])
+                        continue;
+                    const LargeBody q = V.st[base + j];
+                    const double ex = x[k][0] - q.xy.x, ey = x[k][1] - q.xy.y, ez = x[k][2] - q.zvx.x;
+                    const double sep2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                    if (hill_close(sep2, mi, V.m[base + j], inv24m0, rb[k], V.red[base + j]))
+                        fl |= 2;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (own[k])
+                V.flag[base + bk[k]] = k == 0 ? fl : 0;
+    }
+    __syncthreads();
+    int r = 0;
+    if (valid)
+        for (int b = 0; b < n; ++b)
+            r |= V.flag[base + b];
+    __syncthreads();
+    return r;
 }
 
 // Fixed Hermite P(EC)^2 steps (Algorithm 1's loop, Algorithm 2's step) for
@@ -2182,7 +2276,7 @@ __device__ __forceinline__ void large_eval_k(const LargeStepView &V, const int E
 // Every lane commits every iteration (so the pre-step state need not stay
 // live through the evaluations); a system's state is written back as soon
 // as it stops stepping, and its registers are ignored after that.
-template <int K>
+template <int K, bool ADV>
 __global__ __launch_bounds__(kLargeMaxLanes / K) __attribute__((amdgpu_waves_per_eu(FB_LARGE_WAVES)))
 void k_plain_large(Bucket B, StepParams P, int S)
 {
@@ -2255,13 +2349,14 @@ void k_plain_large(Bucket B, StepParams P, int S)
             for (int cc = 0; cc < 3; ++cc)
                 predict_comp(cf, x[k][cc], v[k][cc], a0[k][cc], j0[k][cc], xc[k][cc], vc[k][cc],
                              bx[k][cc], bv[k][cc]);
-        large_eval_k<K>(V, E, 0, base, n, act, bk, own, xc, vc, ak, jk);
+        double w[K];
+        large_eval_k<K, false>(V, E, 0, base, n, act, bk, own, xc, vc, ak, jk, w);
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
                 correct_comp(cf, bx[k][cc], bv[k][cc], ak[k][cc], jk[k][cc], xc[k][cc], vc[k][cc]);
-        large_eval_k<K>(V, E, 1, base, n, act, bk, own, xc, vc, ak, jk);
+        large_eval_k<K, ADV>(V, E, 1, base, n, act, bk, own, xc, vc, ak, jk, w);
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -2270,9 +2365,27 @@ void k_plain_large(Bucket B, StepParams P, int S)
                 a0[k][cc] = ak[k][cc];
                 j0[k][cc] = jk[k][cc];
             }
+        double dtp = 0.0;
+        if (ADV && P.adaptive == 1)   // the pairwise rule: max over the system's pairs
+            dtp = P.eta * rsqrt_nr(large_sys_reduce<K, true>(V.red, base, n, valid, bk, own, w));
+        if (ADV && P.adaptive == 2) { // Eq. 5: sum over the system's bodies
+            double q[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double aa = fma(ak[k][2], ak[k][2], fma(ak[k][1], ak[k][1], ak[k][0] * ak[k][0]));
+                const double jj = fma(jk[k][2], jk[k][2], fma(jk[k][1], jk[k][1], jk[k][0] * jk[k][0]));
+                q[k] = jj / aa;
+            }
+            dtp = P.eta * rsqrt_nr(large_sys_reduce<K, false>(V.red, base, n, valid, bk, own, q));
+        }
         if (act) {
-            finish_step(c, P, last, hs, 0.0);
+            finish_step(c, P, last, hs, dtp);
             pending = true;
+        }
+        if (ADV) {
+            const int fl = large_stop_flags<K>(V, base, n, valid, bk, own, x, v, P);
+            if (act && fl)
+                c.status = status_of_flags(fl);
         }
     }
     if (pending)
@@ -2284,8 +2397,9 @@ void k_plain_large(Bucket B, StepParams P, int S)
     __syncthreads();
     if (valid && h == 0) {   // the lane of the star
         int fl = 0;
-        for (int b = 0; b < n; ++b)
-            fl |= V.flag[base + b];
+        if (!ADV)            // (with ADV the stop flags checked every step)
+            for (int b = 0; b < n; ++b)
+                fl |= V.flag[base + b];
         if (fl)
             c.status = ST_NONFINITE;
         store_clock(B, slot, c);
@@ -2389,6 +2503,74 @@ __device__ __forceinline__ void large_load_xv(const Bucket &B, const LargeLane &
     for (int c = 0; c < 3; ++c) {
         x[c] = B.st[((R_X + c) * n + l.b) * pitch + l.slot];
         v[c] = B.st[((R_V + c) * n + l.b) * pitch + l.slot];
+    }
+}
+
+// Run start of a large-n bucket (one body per lane): the clock part on the
+// star's lane, then, for systems that need one, the first adaptive step from
+// the stored (a0, j0) (Eq. 5) or from the pairwise rule at the current state
+// (the proposals of k_begin_run).
+__global__ __launch_bounds__(kLargeMaxLanes) void k_begin_run_large(Bucket B, int S,
+                                                                    int fixed_steps,
+                                                                    long long n_steps,
+                                                                    double t_end, double dt,
+                                                                    int adaptive, double eta)
+{
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    if (l.valid && l.b == 0)
+        V.flag[l.base] = begin_run_clock(B, l.slot, fixed_steps, n_steps, t_end, dt, adaptive);
+    __syncthreads();
+    const bool need = l.valid && V.flag[l.base] != 0;
+    if (!__syncthreads_or(need))
+        return;
+    const size_t pitch = B.pitch;
+    double mi, x[3], v[3];
+    large_load_xv(B, l, mi, x, v);
+    double q = 0.0;
+    if (adaptive == 2) {
+        if (l.valid) {
+            double a[3], jk[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[c] = B.st[((R_A + c) * n + l.b) * pitch + l.slot];
+                jk[c] = B.st[((R_J + c) * n + l.b) * pitch + l.slot];
+            }
+            q = fma(jk[2], jk[2], fma(jk[1], jk[1], jk[0] * jk[0])) /
+                fma(a[2], a[2], fma(a[1], a[1], a[0] * a[0]));
+        }
+    } else {
+        V.m[l.tid] = mi;
+        V.xy[l.tid] = make_double2(x[0], x[1]);
+        V.zvx[l.tid] = make_double2(x[2], v[0]);
+        V.vyvz[l.tid] = make_double2(v[1], v[2]);
+        __syncthreads();
+        if (l.valid) {
+            for (int j = 0; j < n; ++j) {
+                if (j == l.b)
+                    continue;
+                const double2 p0 = V.xy[l.base + j], p1 = V.zvx[l.base + j],
+                              p2 = V.vyvz[l.base + j];
+                const double rx = p0.x - x[0], ry = p0.y - x[1], rz = p1.x - x[2];
+                const double ux = p1.y - v[0], uy = p2.x - v[1], uz = p2.y - v[2];
+                const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+                const double ru = fma(rz, uz, fma(ry, uy, rx * ux));
+                const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+                const double ri = rsqrt_nr(r2);
+                const double ri2 = ri * ri;
+                const double al = 3.0 * ru * ri2;
+                q = fmax(q, fma(al, ru, u2) * ri2);
+            }
+        }
+    }
+    V.red[l.tid] = q;
+    __syncthreads();
+    if (need && l.b == 0) {
+        double r = V.red[l.base];
+        for (int b = 1; b < n; ++b)
+            r = adaptive == 2 ? r + V.red[l.base + b] : fmax(r, V.red[l.base + b]);
+        B.dtn[l.slot] = eta * rsqrt_nr(r);
     }
 }
 
@@ -2597,10 +2779,12 @@ hipError_t launch_begin_run(const Bucket &B, int fixed_steps, long long n_steps,
     if (B.count == 0)
         return hipSuccess;
     if (B.n > kMaxBodies) {
-        if (!fixed_steps && adaptive)
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, 1, grid, T, S))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_begin_run_large, grid_for(B.count, 64), dim3(64), 0, s, B,
-                           fixed_steps, n_steps, t_end, dt);
+        hipLaunchKernelGGL(k_begin_run_large, grid, dim3(T), large_lds_bytes(T), s, B, S,
+                           fixed_steps, n_steps, t_end, dt, adaptive, eta);
         return hipGetLastError();
     }
 #define FB_L(NN)                                                                        \
@@ -2622,12 +2806,17 @@ hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const
         dim3 grid;
         int T, S;
         const int K = large_bodies_per_lane(B.n);
-        if (adv || !large_launch(B, K, grid, T, S))
+        if (!large_launch(B, K, grid, T, S))
             return hipErrorInvalidValue;
-        if (K == 2)
-            hipLaunchKernelGGL(k_plain_large<2>, grid, dim3(T), large_lds_bytes(2 * T), s, B, P, S);
+        const size_t lds = large_lds_bytes(K * T);
+        if (K == 2 && adv)
+            hipLaunchKernelGGL((k_plain_large<2, true>), grid, dim3(T), lds, s, B, P, S);
+        else if (K == 2)
+            hipLaunchKernelGGL((k_plain_large<2, false>), grid, dim3(T), lds, s, B, P, S);
+        else if (adv)
+            hipLaunchKernelGGL((k_plain_large<1, true>), grid, dim3(T), lds, s, B, P, S);
         else
-            hipLaunchKernelGGL(k_plain_large<1>, grid, dim3(T), large_lds_bytes(T), s, B, P, S);
+            hipLaunchKernelGGL((k_plain_large<1, false>), grid, dim3(T), lds, s, B, P, S);
         return hipGetLastError();
     }
     if (mapping == MAP_SPL && B.n <= (adv ? kMaxSplAdv : kMaxSplBodies)) {

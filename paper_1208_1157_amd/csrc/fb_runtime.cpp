@@ -639,13 +639,13 @@ bool has_large(const fb_ensemble *e)
     return false;
 }
 
-// Systems of more than kMaxBodies bodies run the large-n kernels: fixed
-// Hermite steps on the plain schedule.
+// Systems of more than kMaxBodies bodies run the large-n kernels: Hermite
+// steps on the plain schedule.
 fb_status check_large(const fb_ensemble *e, const fb_opts &o)
 {
-    if (has_large(e) && (o.adaptive || o.stop_rules || o.schedule != FB_SCHED_PLAIN))
-        return fail(FB_E_INVAL, "systems of more than %d bodies take fixed steps on the plain "
-                                "schedule without stop rules", kMaxBodies);
+    if (has_large(e) && o.schedule != FB_SCHED_PLAIN)
+        return fail(FB_E_INVAL, "systems of more than %d bodies run the plain schedule",
+                    kMaxBodies);
     return FB_OK;
 }
 

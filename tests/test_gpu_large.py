@@ -2,8 +2,9 @@
 body per lane across a workgroup, each pair evaluated from both sides)
 against the Hermite oracle: fixed-step parity for 17..512 bodies beside
 small systems in one ensemble, a sampled full-size disk ensemble, the
-set-up evaluation, the last shortened step of a run to t_end, diagnostics,
-logging, invisible quanta, and the calls that refuse such systems."""
+set-up evaluation, the last shortened step of a run to t_end, adaptive
+steps under both rules, the stop rules, diagnostics, logging, invisible
+quanta, and the calls that refuse such systems."""
 import math
 import sys
 
@@ -169,9 +170,8 @@ def test_quanta_are_bitwise_invisible(fb):
 def test_refusals(fb):
     ens = concat([gen.planetesimal_disk(2, 20, seed=91), gen.three_body(3, seed=92)])
     E = fb.from_gen(ens)
-    bad = [lambda: E.integrate(1.0, 0.01, fb.Opts(adaptive=True)),
-           lambda: E.integrate_steps(10, 0.01, fb.Opts(stop_rules=fb.STOP_EJECT)),
-           lambda: E.integrate_steps(10, 0.01, fb.Opts(schedule=fb.SCHED_PERSISTENT)),
+    bad = [lambda: E.integrate_steps(10, 0.01, fb.Opts(schedule=fb.SCHED_PERSISTENT)),
+           lambda: E.integrate(1.0, 0.01, fb.Opts(adaptive=True, schedule=fb.SCHED_PERSISTENT)),
            lambda: E.integrate_rkck_steps(10, 0.01),
            lambda: E.integrate_rkck(1.0, 0.01, 1e-9),
            lambda: E.integrate_mvs(10, 0.01),
@@ -186,3 +186,50 @@ def test_refusals(fb):
         with pytest.raises(fb.FewbodyError) as ei:
             S.submit_gen(gen.planetesimal_disk(1, 17, seed=93), 1.0, 0.01)
         assert ei.value.code == fb.E_INVAL
+
+
+@pytest.mark.parametrize("rule", [1, 2])
+def test_adaptive_parity(fb, ora, rule):
+    """Adaptive steps (the pairwise rule, or Eq. 5) for 20..130 bodies: the
+    same accepted-step counts as the oracle and parity to 1e-10."""
+    ens = concat([gen.planetesimal_disk(4, 20, seed=94), gen.planetesimal_disk(3, 41, seed=95),
+                  gen.planetesimal_disk(2, 130, seed=96), gen.three_body(6, seed=97)])
+    eta = 0.01 if rule == 1 else 1.7e-2
+    t_end = 0.5
+    say("large-n adaptive", rule)
+    E = fb.from_gen(ens)
+    E.integrate(t_end, 0.0, fb.Opts(adaptive=rule, eta=eta, steps_per_quantum=7))
+    st = E.state()
+    E.close()
+    assert np.all(st["status"] == fb.DONE) and np.all(st["t"] == t_end)
+    off = ens.offsets
+    for s in range(ens.n_sys):
+        o = ora.integrate_adaptive(*ens.system(s), t_end, eta=eta, stop_rules=0, paper_rule=rule == 2)
+        assert o["status"] == ora.DONE and o["steps"] == st["steps"][s], (s, o["steps"], st["steps"][s])
+        sl = slice(off[s], off[s + 1])
+        check(ens.subset([s]), st["pos"][sl], st["vel"][sl], o["pos"], o["vel"], f"system {s}")
+
+
+def test_stop_rules(fb, ora):
+    """A disk with a body beyond r_eject, one with two bodies inside a
+    mutual Hill radius, one with a non-finite-free ordinary run: the same
+    status, step count and state as the oracle."""
+    base = gen.planetesimal_disk(3, 24, seed=98)
+    pos, vel = base.pos.copy(), base.vel.copy()
+    off = base.offsets
+    pos[off[0] + 5] = [150.0, 0.0, 0.0]            # ejected once it has taken a step
+    vel[off[0] + 5] = [0.0, 0.0, 0.0]
+    pos[off[1] + 7] = pos[off[1] + 6] + [1e-3, 0.0, 0.0]   # well inside a mutual Hill radius
+    vel[off[1] + 7] = vel[off[1] + 6]
+    ens = gen.Ensemble(base.n_body, base.mass, pos, vel)
+    t_end = 0.3
+    E = fb.from_gen(ens)
+    E.integrate(t_end, 0.0, fb.Opts(adaptive=1, eta=0.01, stop_rules=3, r_eject=100.0))
+    st = E.state()
+    E.close()
+    assert list(st["status"]) == [fb.EJECTED, fb.ENCOUNTER, fb.DONE]
+    for s in range(ens.n_sys):
+        o = ora.integrate_adaptive(*ens.system(s), t_end, eta=0.01, stop_rules=3, r_eject=100.0)
+        assert o["status"] == st["status"][s] and o["steps"] == st["steps"][s], (s, o["status"], o["steps"])
+        sl = slice(off[s], off[s + 1])
+        check(ens.subset([s]), st["pos"][sl], st["vel"][sl], o["pos"], o["vel"], f"system {s}")
