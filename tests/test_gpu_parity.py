@@ -112,6 +112,41 @@ def test_parity_full_size_ragged_sampled(plans, ora):
     assert_parity(sub.n_body, st["pos"][rows], st["vel"][rows], X, V, label="65536 ragged sampled")
 
 
+def test_parity_full_size_lifetimes_sampled(plans, ora):
+    """All 65536 uneven-lifetime systems in the benchmark's launch
+    configuration (persistent schedule, in-kernel compaction, 2000-step
+    quanta, adaptive steps, both stop rules) over 3 inner orbits; 256 sampled
+    systems recomputed by the oracle.  Systems whose discrete decisions agree
+    (status, step count) match to 1e-10."""
+    fb = plans
+    ens, p = gen.workload("lifetimes_65536x4-8")
+    t_end = 2 * math.pi * 3
+    say("lifetimes_65536 sampled, persistent + compaction, 3 orbits")
+    E = fb.from_gen(ens)
+    E.integrate(t_end, 0.0, fb.Opts(adaptive=True, eta=p["eta"], stop_rules=3, r_eject=p["r_eject"],
+                                    schedule=fb.SCHED_PERSISTENT, steps_per_quantum=2000, compact=True))
+    st = E.state()
+    E.close()
+    assert np.all(st["status"] != fb.ACTIVE)
+    rng = np.random.default_rng(4)
+    idx = np.sort(rng.choice(ens.n_sys, 256, replace=False))
+    off = ens.offsets
+    agree, stopped = 0, 0
+    for s in idx:
+        s = int(s)
+        o = ora.integrate_adaptive(*ens.system(s), t_end=t_end, eta=p["eta"], stop_rules=3,
+                                   r_eject=p["r_eject"])
+        if o["status"] != st["status"][s] or o["steps"] != st["steps"][s]:
+            continue
+        agree += 1
+        stopped += o["status"] != ora.DONE
+        sl = slice(off[s], off[s + 1])
+        assert_parity([ens.n_body[s]], st["pos"][sl], st["vel"][sl], o["pos"], o["vel"],
+                      label=f"lifetimes system {s}")
+    say("agree", agree, "of", len(idx), "stopped by a rule", stopped)
+    assert agree >= 0.97 * len(idx), agree
+
+
 @pytest.mark.parametrize("steps", [1000, 20000])
 def test_energy_drift_within_twice_oracle(fb, ora, steps):
     """Energy drift |dE/E| of the GPU run within 2x the oracle's, over the
