@@ -33,7 +33,7 @@
 // Partner-loop unroll of the body-per-lane evaluation: full unrolling lets
 // the scheduler hoist every partner's LDS loads and costs occupancy.
 #ifndef FB_BPL_UNROLL
-#define FB_BPL_UNROLL 2
+#define FB_BPL_UNROLL 1
 #endif
 // Pairs per scheduling group in the system-per-lane evaluation of n >= 5.
 #ifndef FB_SPL_PAIR_GROUP
