@@ -47,7 +47,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 # reading) recorded in profiles/, keyed by the kernel source they measured.
 MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1,
                     "1c9dff3d544099cf": 92417308.4, "234f298587126ea3": 92405022.4,
-                    "b0cf1370d8600140": 92417213.2}
+                    "b0cf1370d8600140": 92417213.2, "d75718a170f1a208": 92400808.0}
 # Hardware counters of the same kernel on this workload (profiles/), keyed the
 # same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
 # lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
@@ -59,6 +59,8 @@ MEASURED_COUNTERS = {
                          "shader_clock_ghz": 1.996, "valu_insts_per_system_step": 388.01},
     "b0cf1370d8600140": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9729,
                          "shader_clock_ghz": 1.977, "valu_insts_per_system_step": 388.01},
+    "d75718a170f1a208": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9685,
+                         "shader_clock_ghz": 1.999, "valu_insts_per_system_step": 388.01},
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
@@ -265,6 +267,38 @@ def rkck_extras(fb, gen, torch, log, steps=2000):
     return out
 
 
+def logging_extras(fb, gen, torch, log, steps=20000, every=200):
+    """The monitor with on-device data reduction (Sections 4.3 and 4.4) on
+    the headline ensemble: records every `every` steps of the star's
+    line-of-sight velocity, or of energy and angular momentum, against the
+    unlogged run.  The run leaves its records in a device buffer; their copy
+    to pinned host memory is timed on its own."""
+    ens, p = gen.workload("homog_131072x3")
+    t0, _ = timed(fb, torch, ens, lambda E: E.integrate_steps(steps, p["dt"]))
+    records = 1 + steps // every
+    out = {"steps": steps, "every": every, "records_per_system": records, "unlogged_seconds": t0}
+    full_state = 8 * (1 + 6 * 3)   # bytes of one full-state record of a 3-body system
+    for name, kind in (("rv", fb.LOG_RV), ("energy", fb.LOG_ENERGY)):
+        held = {}
+        t, _ = timed(fb, torch, ens, lambda E: held.update(
+            buf=E.integrate_steps_logged(steps, p["dt"], every, kind=kind, to_host=False)[0]))
+        buf = held["buf"]
+        host = torch.empty(buf.numel(), dtype=torch.uint8, pin_memory=True)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        host.copy_(buf)
+        copy_s = time.perf_counter() - c0
+        down = buf.numel()
+        out[name] = {"seconds": t, "overhead": t / t0 - 1.0, "bytes_to_host": down,
+                     "host_copy_seconds": copy_s, "host_copy_gb_per_s": down / copy_s / 1e9,
+                     "bytes_as_full_states": ens.n_sys * records * full_state,
+                     "records_per_s": ens.n_sys * records / t}
+        log(f"[bench] logging {name}: {t:.4f} s vs {t0:.4f} s unlogged; {down / 1e6:.0f} MB of records "
+            f"({ens.n_sys * records * full_state / down:.1f}x less than full states) copied in {copy_s:.4f} s")
+        del buf, host, held
+    return out
+
+
 def large_n_extras(fb, gen, torch, log):
     """The large-n gravitation (systems of 17..512 bodies, Section 4.2's
     second variant): fixed Hermite steps (dt 2pi/1000) on planetesimal disks.
@@ -460,6 +494,7 @@ def main():
         extras["mvs"] = mvs_extras(fb, gen, torch, log)
         extras["rkck"] = rkck_extras(fb, gen, torch, log)
         extras["large_n"] = large_n_extras(fb, gen, torch, log)
+        extras["logging"] = logging_extras(fb, gen, torch, log)
     if extras:
         result["extras"] = extras
     if not args.no_cpu:

@@ -267,12 +267,14 @@ class Ensemble:
         _check(_lib.fb_integrate_steps(self._handle, int(n_steps), float(dt), ctypes.byref(o)))
 
     def integrate_steps_logged(self, n_steps, dt, every, kind=LOG_RV, los=(0.0, 0.0, 1.0),
-                               opts: Opts | None = None, max_records=None):
+                               opts: Opts | None = None, max_records=None, to_host=True):
         """fb_integrate_steps with a monitor that logs every `every` steps
         into a device buffer (torch-owned); returns the records on the host:
         LOG_RV -> (t, rv) [n_sys, R] each; LOG_ENERGY -> (t, E, L)
         [n_sys, R], [n_sys, R], [n_sys, R, 3]; LOG_STATE -> (t [n_sys, R],
-        pos [R, N, 3], vel [R, N, 3])."""
+        pos [R, N, 3], vel [R, N, 3]).  With to_host=False the call returns
+        at once with (device buffer, records written), the records still in
+        HBM in the layout fb_log_bytes describes."""
         if every < 1:
             raise FewbodyError(E_INVAL, "every must be >= 1")
         R = max_records or (1 + n_steps // every + (1 if n_steps % every else 0))
@@ -281,10 +283,12 @@ class Ensemble:
         n_rec = ctypes.c_int32()
         _check(_lib.fb_integrate_steps_logged(self._handle, int(n_steps), float(dt), ctypes.byref(o),
                                               ctypes.byref(spec), ctypes.byref(n_rec)))
+        if not to_host:
+            return buf, n_rec.value
         return self._read_log(buf, kind, R, n_rec.value)
 
     def integrate_to_times(self, t_obs, dt=0.0, kind=LOG_RV, los=(0.0, 0.0, 1.0),
-                           opts: Opts | None = None):
+                           opts: Opts | None = None, to_host=True):
         """fb_integrate_to_times: integrate to each time of t_obs in turn and
         record every system there; returns the records as
         integrate_steps_logged does (R = len(t_obs))."""
@@ -295,6 +299,8 @@ class Ensemble:
         n_rec = ctypes.c_int32()
         _check(_lib.fb_integrate_to_times(self._handle, int(t.shape[0]), _ptr(t), float(dt), ctypes.byref(o),
                                           ctypes.byref(spec), ctypes.byref(n_rec)))
+        if not to_host:
+            return buf, n_rec.value
         return self._read_log(buf, kind, R, n_rec.value)
 
     def _log_buffer(self, kind, R, los, every):
