@@ -302,7 +302,9 @@ fb_status fb_ensemble_destroy(fb_ensemble *e);
  * allows; FB_MAP_BODY_PER_LANE: <= 128 VGPRs, body-per-lane tiles only;
  * FB_MAP_AUTO: the former when every bucket allows it and its tiles give
  * every SIMD a wavefront), plus waves per workgroup and workgroups per CU
- * (1..32, 0 = default).  Plans are process-wide; the autotuner sets them. */
+ * (1..32, 0 = default).  In the system-per-lane class a body count whose own
+ * plan is FB_MAP_BODY_PER_LANE runs body-per-lane tiles.  Plans are
+ * process-wide; the autotuner sets them. */
 fb_status fb_set_plan(int32_t n, int32_t mapping, int32_t waves_per_group,
                       int32_t groups_per_cu);
 fb_status fb_get_plan(int32_t n, int32_t *mapping, int32_t *waves_per_group,

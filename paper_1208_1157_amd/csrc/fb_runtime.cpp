@@ -465,8 +465,10 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     for (int i = 0; i < nbk; ++i) {
         const int n = e->buckets[i].n;
         const int m = get_plan(n).mapping;
-        // in the system-per-lane class every bucket that can runs system-per-lane
-        mapping[i] = (n <= spl_lim && (m == MAP_SPL || cls == 1)) ? MAP_SPL : MAP_BPL;
+        // in the system-per-lane class every bucket that can runs system-per-lane,
+        // unless its plan asks for body-per-lane
+        mapping[i] = (n <= spl_lim && m != MAP_BPL && (m == MAP_SPL || cls == 1)) ? MAP_SPL
+                                                                                 : MAP_BPL;
         counts[i] = e->buckets[i].count;
     }
     ident.reserve(e->L.list_total);

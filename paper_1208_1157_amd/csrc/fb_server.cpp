@@ -505,7 +505,9 @@ fb_status grow(T *&p, size_t &cap, size_t need)
 int server_mapping(const fb_server *S, int n)
 {
     const int lim = persistent_spl_limit(S->cls, 0);
-    return (n <= lim && (S->mapping[n] == MAP_SPL || S->cls == 1)) ? MAP_SPL : MAP_BPL;
+    // an explicit body-per-lane plan wins over the class's system-per-lane default
+    return (n <= lim && S->mapping[n] != MAP_BPL && (S->mapping[n] == MAP_SPL || S->cls == 1))
+               ? MAP_SPL : MAP_BPL;
 }
 
 // One quantum.  Returns the requests it finished (reached their step count
