@@ -360,6 +360,9 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the ragged (autotuned, plain vs persistent) and uneven-lifetimes "
                          "(plain vs compaction) comparisons")
+    ap.add_argument("--extra", action="append", default=[],
+                    choices=["ragged", "lifetimes", "paper_ics", "mvs", "rkck", "large_n", "logging"],
+                    help="run only this extra workload (repeatable)")
     ap.add_argument("--lifetimes-orbits", type=float, default=100.0,
                     help="horizon of the uneven-lifetimes extra in inner orbits (the workload's is 1e4)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
@@ -485,16 +488,19 @@ def main():
         result["p50_latency_s"] = rep["p50_latency_s"]
         result["p99_latency_s"] = rep["p99_latency_s"]
         extras["serving"] = rep
-    if args.extras:
-        extras["ragged"] = ragged_extras(fb, gen, torch, log)
-        restore_plans()
-        extras["lifetimes"] = lifetimes_extras(fb, gen, torch, log, orbits=args.lifetimes_orbits)
-        restore_plans()
-        extras["paper_ics"] = paper_ic_extras(fb, gen, torch, log)
-        extras["mvs"] = mvs_extras(fb, gen, torch, log)
-        extras["rkck"] = rkck_extras(fb, gen, torch, log)
-        extras["large_n"] = large_n_extras(fb, gen, torch, log)
-        extras["logging"] = logging_extras(fb, gen, torch, log)
+    runs = [
+        ("ragged", lambda: ragged_extras(fb, gen, torch, log)),
+        ("lifetimes", lambda: lifetimes_extras(fb, gen, torch, log, orbits=args.lifetimes_orbits)),
+        ("paper_ics", lambda: paper_ic_extras(fb, gen, torch, log)),
+        ("mvs", lambda: mvs_extras(fb, gen, torch, log)),
+        ("rkck", lambda: rkck_extras(fb, gen, torch, log)),
+        ("large_n", lambda: large_n_extras(fb, gen, torch, log)),
+        ("logging", lambda: logging_extras(fb, gen, torch, log)),
+    ]
+    for name, fn in runs:
+        if args.extras or name in args.extra:
+            extras[name] = fn()
+            restore_plans()
     if extras:
         result["extras"] = extras
     if not args.no_cpu:
