@@ -20,8 +20,9 @@
  * body count.  Larger ones run the large-n gravitation (Section 4.2's second
  * variant: one body per lane across a workgroup, each pair evaluated from
  * both sides): Hermite steps, fixed or adaptive, with stop rules, monitors
- * and diagnostics, on the plain schedule.  The persistent schedule, MVS,
- * Runge-Kutta, autotuning and the server reject ensembles holding such
+ * and diagnostics; on the persistent schedule they run as plain launches
+ * inside every quantum, beside the fused launch of the smaller systems.
+ * MVS, Runge-Kutta, autotuning and the server reject ensembles holding such
  * systems with FB_E_INVAL.
  * Flat body arrays are body-major: body b of system s is row off[s] + b with
  * off the exclusive prefix sum of n_body; pos/vel/acc/jerk rows hold x,y,z.

@@ -1047,7 +1047,7 @@ __global__ void k_build_tiles(const Bucket *__restrict__ buckets, int nb,
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += blockDim.x)
-        AL.next_count[i] = 0;
+        AL.next_count[order[i]] = 0;
 }
 
 __global__ void k_fill_int(int *p, int n, int value)
@@ -2923,6 +2923,8 @@ hipError_t launch_build_tiles(const Bucket *d_buckets, int n_buckets, const int 
                               const int *d_mapping, ActiveLists L, Tile *d_tiles, int *d_ntiles,
                               int *d_head, hipStream_t s)
 {
+    if (n_buckets < 0 || n_buckets > kMaxBodies + 1)   // the kernel's tables hold kMaxBodies + 2
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_build_tiles, dim3(1), dim3(256), 0, s, d_buckets, n_buckets, d_order,
                        d_mapping, L, d_tiles, d_ntiles, d_head);
     return hipGetLastError();

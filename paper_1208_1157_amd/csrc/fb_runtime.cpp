@@ -447,11 +447,19 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     const int nbk = (int)e->buckets.size();
     if (nbk == 0)
         return FB_OK;
+    // Buckets are laid out in descending n: the large-n ones (n > kMaxBodies)
+    // come first and run their own plain launches inside every quantum; the
+    // fused launch's tile queue covers the others.
+    int n_large = 0;
+    while (n_large < nbk && e->buckets[n_large].n > kMaxBodies)
+        ++n_large;
+    const int nb_small = nbk - n_large;
+    const std::vector<Bucket> small(e->buckets.begin() + n_large, e->buckets.end());
     const Plan p0 = get_plan(0);
     const int W = std::max(1, std::min(4, p0.waves_per_group));
     const bool adv = o.adaptive || o.stop_rules;
     const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
-    const int cls = persistent_class(p0, e->buckets, adv, e->num_cu);
+    const int cls = persistent_class(p0, small, adv, e->num_cu);
     const int spl_lim = persistent_spl_limit(cls, adv ? 1 : 0);
     int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
     const int occ = persistent_max_groups_per_cu(adv ? 1 : 0, cls, W);
@@ -460,10 +468,12 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     const int grid = std::max(1, gpc * e->num_cu);
     const StepParams P = make_params(o, quantum);
 
-    // mapping per bucket, initial lists (identity) and counts
-    std::vector<int> mapping(nbk), counts(nbk), ident;
-    for (int i = 0; i < nbk; ++i) {
+    // mapping per bucket, tile order (the small buckets), initial lists
+    // (identity) and counts
+    std::vector<int> mapping(nbk, MAP_BPL), counts(nbk, 0), order, ident;
+    for (int i = n_large; i < nbk; ++i) {
         const int n = e->buckets[i].n;
+        order.push_back(i);
         const int m = get_plan(n).mapping;
         // in the system-per-lane class every bucket that can runs system-per-lane,
         // unless its plan asks for body-per-lane
@@ -477,6 +487,9 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
             ident.push_back(s);
     FB_HIP(hipMemcpyAsync(e->d_mapping, mapping.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
                           e->stream));
+    if (nb_small)
+        FB_HIP(hipMemcpyAsync(e->d_order, order.data(), sizeof(int) * nb_small,
+                              hipMemcpyHostToDevice, e->stream));
     FB_HIP(hipMemcpyAsync(e->d_lists[0], ident.data(), sizeof(int) * ident.size(),
                           hipMemcpyHostToDevice, e->stream));
     FB_HIP(hipMemcpyAsync(e->d_counts[0], counts.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
@@ -500,8 +513,15 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     auto quantum_launch = [&](hipStream_t s, int k) -> hipError_t {
         if (!compact)
             k = 0;
-        hipError_t err = launch_build_tiles(e->d_buckets, nbk, e->d_order, e->d_mapping, AL[k],
-                                            e->d_tiles, d_ntiles, d_head, s);
+        for (int i = 0; i < n_large; ++i) {
+            const hipError_t err = launch_plain(e->buckets[i], MAP_BPL, 1, P, s);
+            if (err != hipSuccess)
+                return err;
+        }
+        if (nb_small == 0)
+            return hipSuccess;
+        hipError_t err = launch_build_tiles(e->d_buckets, nb_small, e->d_order, e->d_mapping,
+                                            AL[k], e->d_tiles, d_ntiles, d_head, s);
         if (err != hipSuccess)
             return err;
         ActiveLists al = AL[k];
@@ -552,17 +572,29 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
         }
         long long act = 0;
         if (compact) {
-            // survivors of the second quantum sit in counts[0]
-            hipError_t err = hipMemcpyAsync(e->h_pinned + 8, e->d_counts[0], sizeof(int) * nbk,
-                                            hipMemcpyDeviceToHost, e->stream);
+            // survivors of the second quantum sit in counts[0] (the small
+            // buckets' entries; at most kMaxBodies - 1 of them)
+            hipError_t err = hipSuccess;
+            if (nb_small)
+                err = hipMemcpyAsync(e->h_pinned + 8, e->d_counts[0] + n_large,
+                                     sizeof(int) * nb_small, hipMemcpyDeviceToHost, e->stream);
             if (err == hipSuccess)
                 err = hipStreamSynchronize(e->stream);
             if (err != hipSuccess) {
                 result = hip_fail(err, "active count");
                 break;
             }
-            for (int i = 0; i < nbk; ++i)
+            for (int i = 0; i < nb_small; ++i)
                 act += e->h_pinned[8 + i];
+            if (n_large) {   // the large buckets keep no survivor lists
+                FB_HIP(launch_reset_counter(e->d_ints + 3, 1, e->stream));
+                for (int i = 0; i < n_large; ++i)
+                    FB_HIP(launch_count_active(e->buckets[i], e->d_ints + 3, e->stream));
+                FB_HIP(hipMemcpyAsync(e->h_pinned + 3, e->d_ints + 3, sizeof(int),
+                                      hipMemcpyDeviceToHost, e->stream));
+                FB_HIP(hipStreamSynchronize(e->stream));
+                act += e->h_pinned[3];
+            }
         } else {
             int a = 0;
             result = count_active(e, a);
@@ -641,13 +673,11 @@ bool has_large(const fb_ensemble *e)
     return false;
 }
 
-// Systems of more than kMaxBodies bodies run the large-n kernels: Hermite
-// steps on the plain schedule.
-fb_status check_large(const fb_ensemble *e, const fb_opts &o)
+// Systems of more than kMaxBodies bodies run the large-n kernels (on the
+// persistent schedule as plain launches inside every quantum); nothing is
+// refused for them today.
+fb_status check_large(const fb_ensemble *, const fb_opts &)
 {
-    if (has_large(e) && o.schedule != FB_SCHED_PLAIN)
-        return fail(FB_E_INVAL, "systems of more than %d bodies run the plain schedule",
-                    kMaxBodies);
     return FB_OK;
 }
 

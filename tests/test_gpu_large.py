@@ -3,8 +3,9 @@ body per lane across a workgroup, each pair evaluated from both sides)
 against the Hermite oracle: fixed-step parity for 17..512 bodies beside
 small systems in one ensemble, a sampled full-size disk ensemble, the
 set-up evaluation, the last shortened step of a run to t_end, adaptive
-steps under both rules, the stop rules, diagnostics, logging, invisible
-quanta, and the calls that refuse such systems."""
+steps under both rules, the stop rules, the persistent schedule beside the
+fused launch of small systems, diagnostics, logging, invisible quanta, and
+the calls that refuse such systems."""
 import math
 import sys
 
@@ -170,9 +171,7 @@ def test_quanta_are_bitwise_invisible(fb):
 def test_refusals(fb):
     ens = concat([gen.planetesimal_disk(2, 20, seed=91), gen.three_body(3, seed=92)])
     E = fb.from_gen(ens)
-    bad = [lambda: E.integrate_steps(10, 0.01, fb.Opts(schedule=fb.SCHED_PERSISTENT)),
-           lambda: E.integrate(1.0, 0.01, fb.Opts(adaptive=True, schedule=fb.SCHED_PERSISTENT)),
-           lambda: E.integrate_rkck_steps(10, 0.01),
+    bad = [lambda: E.integrate_rkck_steps(10, 0.01),
            lambda: E.integrate_rkck(1.0, 0.01, 1e-9),
            lambda: E.integrate_mvs(10, 0.01),
            lambda: E.autotune(5, 0.01)]
@@ -233,3 +232,58 @@ def test_stop_rules(fb, ora):
         assert o["status"] == st["status"][s] and o["steps"] == st["steps"][s], (s, o["status"], o["steps"])
         sl = slice(off[s], off[s + 1])
         check(ens.subset([s]), st["pos"][sl], st["vel"][sl], o["pos"], o["vel"], f"system {s}")
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_persistent_schedule_with_small_and_large_systems(fb, ora, compact):
+    """Large systems run as plain launches inside every quantum of the
+    persistent schedule: the whole mix matches the oracle, and the large
+    systems are bitwise the plain schedule's."""
+    ens = concat([gen.ragged_hill(60, seed=99, n_lo=2, n_hi=16), gen.planetesimal_disk(5, 17, seed=100),
+                  gen.planetesimal_disk(3, 40, seed=101), gen.planetesimal_disk(2, 130, seed=102)])
+    dt, nsteps = TWO_PI / 1000, 120
+    say("large-n persistent", compact)
+    out = {}
+    for sched in (fb.SCHED_PLAIN, fb.SCHED_PERSISTENT):
+        E = fb.from_gen(ens)
+        E.integrate_steps(nsteps, dt, fb.Opts(schedule=sched, steps_per_quantum=37, compact=compact))
+        out[sched] = E.state()
+        E.close()
+    st = out[fb.SCHED_PERSISTENT]
+    assert np.all(st["status"] == fb.DONE) and np.all(st["steps"] == nsteps)
+    x, v, _, _ = ora.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, dt, nsteps, nthreads=threads())
+    check(ens, st["pos"], st["vel"], x, v, "persistent mix")
+    big = np.repeat(ens.n_body > 16, ens.n_body)
+    assert np.array_equal(st["pos"][big], out[fb.SCHED_PLAIN]["pos"][big])
+    assert np.array_equal(st["vel"][big], out[fb.SCHED_PLAIN]["vel"][big])
+
+
+def test_persistent_adaptive_stop_rules_large_only_and_mixed(fb, ora):
+    """Adaptive steps with both stop rules under compaction: an ensemble of
+    large systems only (no fused launch at all) and one mixed with small
+    systems; statuses, step counts and states against the oracle."""
+    base = gen.planetesimal_disk(3, 24, seed=98)
+    pos, vel = base.pos.copy(), base.vel.copy()
+    off = base.offsets
+    pos[off[0] + 5] = [150.0, 0.0, 0.0]
+    vel[off[0] + 5] = [0.0, 0.0, 0.0]
+    pos[off[1] + 7] = pos[off[1] + 6] + [1e-3, 0.0, 0.0]
+    vel[off[1] + 7] = vel[off[1] + 6]
+    large = gen.Ensemble(base.n_body, base.mass, pos, vel)
+    mixed_ens = concat([large, gen.three_body(20, seed=103), gen.ragged_hill(10, seed=104, n_lo=4, n_hi=8)])
+    t_end = 0.3
+    opts = fb.Opts(adaptive=1, eta=0.01, stop_rules=3, r_eject=100.0, schedule=fb.SCHED_PERSISTENT,
+                   steps_per_quantum=5, compact=True)
+    for ens in (large, mixed_ens):
+        say("large-n persistent adaptive", ens.n_sys)
+        E = fb.from_gen(ens)
+        E.integrate(t_end, 0.0, opts)
+        st = E.state()
+        E.close()
+        assert list(st["status"][:3]) == [fb.EJECTED, fb.ENCOUNTER, fb.DONE]
+        o_off = ens.offsets
+        for s in range(ens.n_sys):
+            o = ora.integrate_adaptive(*ens.system(s), t_end, eta=0.01, stop_rules=3, r_eject=100.0)
+            assert o["status"] == st["status"][s] and o["steps"] == st["steps"][s], (s, o["status"], o["steps"])
+            sl = slice(o_off[s], o_off[s + 1])
+            check(ens.subset([s]), st["pos"][sl], st["vel"][sl], o["pos"], o["vel"], f"system {s}")
