@@ -22,8 +22,8 @@
  * both sides): Hermite steps, fixed or adaptive, with stop rules, monitors
  * and diagnostics; on the persistent schedule they run as plain launches
  * inside every quantum, beside the fused launch of the smaller systems.
- * MVS, Runge-Kutta, autotuning and the server reject ensembles holding such
- * systems with FB_E_INVAL.
+ * MVS runs them too; Runge-Kutta, autotuning and the server reject
+ * ensembles holding such systems with FB_E_INVAL.
  * Flat body arrays are body-major: body b of system s is row off[s] + b with
  * off the exclusive prefix sum of n_body; pos/vel/acc/jerk rows hold x,y,z.
  * All floating point is IEEE binary64.
@@ -164,8 +164,9 @@ fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
                              const fb_opts *o);
 
 /* Mixed-variable symplectic integration (Section 2.2.3) of every active
- * system by exactly n_steps fixed steps of dt, for systems of at most 8
- * bodies (body 0 the central star).  Each step is the paper's sequence of
+ * system by exactly n_steps fixed steps of dt (body 0 the central star;
+ * one system per lane up to 8 bodies, one body per lane across a workgroup
+ * for 9..FB_MAX_BODIES).  Each step is the paper's sequence of
  * sub-steps: Cartesian drift dt/2, kick dt/2, Keplerian drift dt, kick dt/2,
  * Cartesian drift dt/2, in the democratic heliocentric splitting (Duncan,
  * Levison & Lee 1998): planets follow Kepler orbits about the star (mu =
@@ -178,9 +179,8 @@ fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
  * fb_get_hermite_state fails with FB_E_STATE, and the next Hermite
  * integration converts back and re-evaluates (a0, j0).  o: the quantum (o->
  * steps_per_quantum); adaptive, stop_rules and compact must be 0 and the
- * schedule plain.  FB_E_INVAL if a system has more than 8 bodies.  A planet
- * whose heliocentric orbit is not bound stops its system with status
- * FB_SYS_UNBOUND. */
+ * schedule plain.  A planet whose heliocentric orbit is not bound stops its
+ * system with status FB_SYS_UNBOUND. */
 fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *o);
 
 /* ------------------------------------------------- monitors and logging */

@@ -33,7 +33,7 @@
 #include <math.h>
 #include <stddef.h>
 
-#define ORA_MVS_MAX 64
+#define ORA_MVS_MAX 512
 #define ORA_ACTIVE 0
 #define ORA_DONE 1
 #define ORA_NONFINITE 4

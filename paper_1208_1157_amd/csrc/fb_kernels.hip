@@ -2574,7 +2574,13 @@ __global__ __launch_bounds__(kLargeMaxLanes) void k_begin_run_large(Bucket B, in
     }
 }
 
-// Energy and angular momentum of every system of a large-n bucket.
+__device__ __forceinline__ void large_from_mvs(const LargeView &V, const int T, const LargeLane &l,
+                                               const int n, const double mi, double (&x)[3],
+                                               double (&v)[3]);
+
+// Energy and angular momentum of every system of a large-n bucket, in
+// inertial form or (MVS) in MVS form, converted first.
+template <bool MVS>
 __global__ __launch_bounds__(kLargeMaxLanes) void k_diag_large(Bucket B, int S, double *energy,
                                                      double *angmom)
 {
@@ -2583,6 +2589,10 @@ __global__ __launch_bounds__(kLargeMaxLanes) void k_diag_large(Bucket B, int S, 
     const LargeLane l = large_lane(B, S);
     double mi, x[3], v[3], q[5], sum[5];
     large_load_xv(B, l, mi, x, v);
+    if (MVS) {
+        V.m[l.tid] = mi;
+        large_from_mvs(V, T, l, B.n, mi, x, v);
+    }
     large_energy_terms(V, T, l, B.n, mi, x, v, q);
     large_sum5(V, T, l, B.n, q, sum);
     if (!l.valid || l.b != 0)
@@ -2649,6 +2659,318 @@ __global__ __launch_bounds__(kLargeMaxLanes) void k_log_large(Bucket B, int S,
         r[2] = sum[2];
         r[3] = sum[3];
         r[4] = sum[4];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MVS for larger systems (9..512 bodies): one body per lane across a workgroup
+// ---------------------------------------------------------------------------
+// The sub-steps of Section 2.2.3 as in k_plain_mvs, laid out like the large-n
+// Hermite kernels: each planet's lane drifts it along its own Kepler orbit,
+// the planet-planet accelerations are one-sided partner loops over LDS
+// broadcasts (planets in ascending order; the same values as the paired
+// form), and the sums over a system (the drift's momentum, the centre of
+// mass) are fma chains in body order on the star's lane, broadcast through
+// LDS.  Every lane reaches every barrier: a system's outcome (unbound,
+// Kepler failure) predicates its updates, never the control flow.
+
+// Over bodies b >= b0 of the lane's system: sum of w_b u_b (an fma chain in
+// body order) and the star's own u, to every valid lane.  Three barriers.
+__device__ __forceinline__ void large_sys_wsum3(const LargeView &V, const int T,
+                                                const LargeLane &l, const int n, const int b0,
+                                                const double w, const double (&u)[3],
+                                                double (&sum)[3], double (&star_u)[3])
+{
+    double2 *in0 = V.xy + T, *in1 = V.zvx + T, *res = V.vyvz + T;
+    in0[l.tid] = make_double2(u[0], u[1]);
+    in1[l.tid] = make_double2(u[2], w);
+    __syncthreads();
+    if (l.valid && l.b == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int b = b0; b < n; ++b) {
+            const double2 p = in0[l.base + b], q = in1[l.base + b];
+            s0 = fma(q.y, p.x, s0);
+            s1 = fma(q.y, p.y, s1);
+            s2 = fma(q.y, q.x, s2);
+        }
+        res[l.base] = make_double2(s0, s1);
+        V.red[l.base] = s2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        sum[c] = star_u[c] = 0.0;
+    if (l.valid) {
+        const double2 r = res[l.base], p = in0[l.base], q = in1[l.base];
+        sum[0] = r.x;
+        sum[1] = r.y;
+        sum[2] = V.red[l.base];
+        star_u[0] = p.x;
+        star_u[1] = p.y;
+        star_u[2] = q.x;
+    }
+    __syncthreads();
+}
+
+// OR of a per-lane flag over the lane's system, to every valid lane.
+__device__ __forceinline__ int large_sys_or(const LargeView &V, const LargeLane &l, const int n,
+                                            const int f)
+{
+    V.flag[l.tid] = f;
+    __syncthreads();
+    int r = 0;
+    if (l.valid)
+        for (int b = 0; b < n; ++b)
+            r |= V.flag[l.base + b];
+    __syncthreads();
+    return r;
+}
+
+// Planet-planet acceleration of this lane's planet at heliocentric positions
+// Q (each lane's own, published here); zero on the star's lane.
+__device__ __forceinline__ void large_mvs_acc(const LargeView &V, const LargeLane &l, const int n,
+                                              const double (&Q)[3], double (&acc)[3])
+{
+    V.xy[l.tid] = make_double2(Q[0], Q[1]);
+    V.zvx[l.tid] = make_double2(Q[2], 0.0);
+    __syncthreads();
+    acc[0] = acc[1] = acc[2] = 0.0;
+    if (l.valid && l.b > 0)
+        for (int j = 1; j < n; ++j) {
+            if (j == l.b)
+                continue;
+            const double2 p0 = V.xy[l.base + j], p1 = V.zvx[l.base + j];
+            const double d0 = p0.x - Q[0], d1 = p0.y - Q[1], d2 = p1.x - Q[2];
+            const double sr = rsqrt_nr(fma(d2, d2, fma(d1, d1, d0 * d0)));
+            const double mj = V.m[l.base + j] * (sr * sr * sr);
+            acc[0] = fma(mj, d0, acc[0]);
+            acc[1] = fma(mj, d1, acc[1]);
+            acc[2] = fma(mj, d2, acc[2]);
+        }
+    __syncthreads();
+}
+
+// MVS form -> inertial (x, v) of this lane's body (from_mvs): x_0 = X -
+// sum m_i Q_i / M, x_i = Q_i + x_0, v_0 = Vc - sum m_i V_i / m_0,
+// v_i = V_i + Vc.  V.m must hold the masses.
+__device__ __forceinline__ void large_from_mvs(const LargeView &V, const int T, const LargeLane &l,
+                                               const int n, const double mi, double (&x)[3],
+                                               double (&v)[3])
+{
+    const double one[3] = {mi, 0.0, 0.0};
+    double Ms[3], st[3], sq[3], X[3], sp[3], Vc[3];
+    large_sys_wsum3(V, T, l, n, 0, 1.0, one, Ms, st);
+    large_sys_wsum3(V, T, l, n, 1, mi, x, sq, X);
+    large_sys_wsum3(V, T, l, n, 1, mi, v, sp, Vc);
+    const double M = Ms[0], m0 = l.valid ? V.m[l.base] : 1.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double x0 = X[c] - sq[c] / M;
+        if (l.b == 0) {
+            x[c] = x0;
+            v[c] = Vc[c] - sp[c] / m0;
+        } else {
+            x[c] += x0;
+            v[c] += Vc[c];
+        }
+    }
+}
+
+__device__ __forceinline__ void large_load_rows(const Bucket &B, const LargeLane &l, double &mi,
+                                                double (&x)[3], double (&v)[3], double (&a)[3])
+{
+    mi = 0.0;
+    const size_t pitch = B.pitch;
+    const int n = B.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        x[c] = v[c] = a[c] = 0.0;
+    if (!l.valid)
+        return;
+    mi = B.st[(R_M * n + l.b) * pitch + l.slot];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = B.st[((R_X + c) * n + l.b) * pitch + l.slot];
+        v[c] = B.st[((R_V + c) * n + l.b) * pitch + l.slot];
+        a[c] = B.st[((R_A + c) * n + l.b) * pitch + l.slot];
+    }
+}
+
+__device__ __forceinline__ void large_store_rows(const Bucket &B, const LargeLane &l,
+                                                 const double (&x)[3], const double (&v)[3],
+                                                 const double (&a)[3], bool with_a)
+{
+    if (!l.valid)
+        return;
+    const size_t pitch = B.pitch;
+    const int n = B.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        B.st[((R_X + c) * n + l.b) * pitch + l.slot] = x[c];
+        B.st[((R_V + c) * n + l.b) * pitch + l.slot] = v[c];
+        if (with_a)
+            B.st[((R_A + c) * n + l.b) * pitch + l.slot] = a[c];
+    }
+}
+
+// Inertial -> MVS form of a bucket (to_mvs), with the planet-planet
+// accelerations at Q in the a0 rows.
+__global__ __launch_bounds__(kLargeMaxLanes) void k_mvs_enter_large(Bucket B, int S)
+{
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    double mi, x[3], v[3], a[3];
+    large_load_rows(B, l, mi, x, v, a);
+    V.m[l.tid] = mi;
+    const double one[3] = {mi, 0.0, 0.0};
+    double Ms[3], st[3], sx[3], x0[3], sv[3], v0[3];
+    large_sys_wsum3(V, T, l, n, 0, 1.0, one, Ms, st);
+    large_sys_wsum3(V, T, l, n, 0, mi, x, sx, x0);
+    large_sys_wsum3(V, T, l, n, 0, mi, v, sv, v0);
+    const double M = Ms[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double X = sx[c] / M, Vc = sv[c] / M;
+        if (l.b == 0) {
+            x[c] = X;
+            v[c] = Vc;
+        } else {
+            x[c] -= x0[c];
+            v[c] -= Vc;
+        }
+    }
+    large_mvs_acc(V, l, n, x, a);
+    large_store_rows(B, l, x, v, a, true);
+}
+
+// MVS form -> inertial of a bucket (from_mvs); the a0 rows are left as they are.
+__global__ __launch_bounds__(kLargeMaxLanes) void k_mvs_leave_large(Bucket B, int S)
+{
+    const int T = blockDim.x;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    double mi, x[3], v[3], a[3];
+    large_load_rows(B, l, mi, x, v, a);
+    V.m[l.tid] = mi;
+    large_from_mvs(V, T, l, B.n, mi, x, v);
+    large_store_rows(B, l, x, v, a, false);
+}
+
+// Fixed-step MVS integration, one body per lane, for at most P.quantum steps
+// (the clock of the Hermite kernels; the steps of mvs_step, with the
+// outcomes of a system predicating its updates).
+__global__ __launch_bounds__(kLargeMaxLanes) void k_plain_mvs_large(Bucket B, StepParams P, int S)
+{
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    const bool planet = l.b > 0;
+    double mi, Q[3], W[3], acc[3];
+    large_load_rows(B, l, mi, Q, W, acc);
+    V.m[l.tid] = mi;
+    Clock c;
+    c.status = ST_DONE;
+    if (l.valid)
+        c = load_clock(B, l.slot);
+    __syncthreads();
+    const double m0 = l.valid ? V.m[l.base] : 1.0;
+    const double inv_m0 = 1.0 / m0;
+    // drift of Q (planets) by h sum_j m_j V_j / m0 and of X (star) by h Vc
+    auto drift = [&](const bool on, const double h) {
+        double Pm[3], unused[3];
+        large_sys_wsum3(V, T, l, n, 1, mi, W, Pm, unused);
+        if (!on)
+            return;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (planet)
+                Q[k] += h * Pm[k] * inv_m0;
+            else
+                Q[k] = fma(h, W[k], Q[k]);
+        }
+    };
+    for (int q = 0; q < P.quantum; ++q) {
+        double h = 0.0;
+        bool last = false;
+        const bool act = l.valid && plan_step(c, P, h, last);
+        if (!__syncthreads_or(act))
+            break;
+        const double hh = 0.5 * h;
+        drift(act, hh);
+        if (act && planet)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                W[k] = fma(hh, acc[k], W[k]);
+        int unbound = 0;
+        if (act && planet) {
+            const double r2 = fma(Q[2], Q[2], fma(Q[1], Q[1], Q[0] * Q[0]));
+            const double v2 = fma(W[2], W[2], fma(W[1], W[1], W[0] * W[0]));
+            unbound = (2.0 / sqrt(r2) - v2 / m0 > 0.0) ? 0 : 1;
+        }
+        const int unbound_sys = large_sys_or(V, l, n, unbound);   // every lane: barriers inside
+        const bool undo = act && unbound_sys;
+        if (undo && planet)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                W[k] = fma(-hh, acc[k], W[k]);
+        drift(undo, -hh);
+        const bool go = act && !undo;
+        const int kfail = (go && planet && !kepler_drift(m0, Q, W, h)) ? 1 : 0;
+        const int kfail_sys = large_sys_or(V, l, n, kfail);       // every lane: barriers inside
+        const bool failed = go && kfail_sys;
+        const bool ok = go && !failed;
+        double an[3];
+        large_mvs_acc(V, l, n, Q, an);
+        if (ok && planet)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                acc[k] = an[k];
+                W[k] = fma(hh, acc[k], W[k]);
+            }
+        drift(ok, hh);
+        if (ok)
+            finish_step(c, P, last, h, 0.0);
+        if (undo || failed)
+            c.status = ST_UNBOUND;
+    }
+    const int bad = large_sys_or(V, l, n, (l.valid && !(finite3(Q) && finite3(W))) ? 1 : 0);
+    if (!l.valid)
+        return;
+    if (bad)
+        c.status = ST_NONFINITE;
+    large_store_rows(B, l, Q, W, acc, true);
+    if (l.b == 0)
+        store_clock(B, l.slot, c);
+}
+
+// State read-back of a bucket in MVS form, converted to inertial (x, v) on
+// the way out (the layouts of k_unpack).
+__global__ __launch_bounds__(kLargeMaxLanes) void k_unpack_mvs_large(
+    Bucket B, int S, const long long *__restrict__ orig_off, double *pos, double *vel, double *t,
+    int *status, long long *steps)
+{
+    const int T = blockDim.x;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    double mi, x[3], v[3], a[3];
+    large_load_rows(B, l, mi, x, v, a);
+    V.m[l.tid] = mi;
+    large_from_mvs(V, T, l, B.n, mi, x, v);
+    if (!l.valid)
+        return;
+    const int o = B.orig[l.slot];
+    const long long base = orig_off[o];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const size_t row = 3 * (base + l.b) + c;
+        if (pos) pos[row] = x[c];
+        if (vel) vel[row] = v[c];
+    }
+    if (l.b == 0) {
+        if (t) t[o] = B.t[l.slot];
+        if (status) status[o] = B.status[l.slot];
+        if (steps) steps[o] = B.steps[l.slot];
     }
 }
 
@@ -2952,13 +3274,17 @@ hipError_t launch_diag(const Bucket &B, double *energy, double *angmom, bool mvs
 {
     if (B.count == 0)
         return hipSuccess;
-    if (B.n > kMaxBodies) {
+    if (B.n > kMaxBodies || (mvs_form && B.n > kMaxMvsBodies)) {
         dim3 grid;
         int T, S;
-        if (mvs_form || !large_launch(B, 1, grid, T, S))
+        if (!large_launch(B, 1, grid, T, S))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_diag_large, grid, dim3(T), large_lds_bytes(T), s, B, S, energy,
-                           angmom);
+        if (mvs_form)
+            hipLaunchKernelGGL(k_diag_large<true>, grid, dim3(T), large_lds_bytes(T), s, B, S,
+                               energy, angmom);
+        else
+            hipLaunchKernelGGL(k_diag_large<false>, grid, dim3(T), large_lds_bytes(T), s, B, S,
+                               energy, angmom);
         return hipGetLastError();
     }
     if (mvs_form) {
@@ -2988,6 +3314,14 @@ hipError_t launch_mvs_enter(const Bucket &B, hipStream_t s)
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxMvsBodies) {
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, 1, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_mvs_enter_large, grid, dim3(T), large_lds_bytes(T), s, B, S);
+        return hipGetLastError();
+    }
 #define FB_L(NN) hipLaunchKernelGGL(k_mvs_enter<NN>, grid_for(B.count, 64), dim3(64), 0, s, B)
     FB_SWITCH_MVS(B.n, FB_L)
 #undef FB_L
@@ -2998,6 +3332,14 @@ hipError_t launch_mvs_leave(const Bucket &B, hipStream_t s)
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxMvsBodies) {
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, 1, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_mvs_leave_large, grid, dim3(T), large_lds_bytes(T), s, B, S);
+        return hipGetLastError();
+    }
 #define FB_L(NN) hipLaunchKernelGGL(k_mvs_leave<NN>, grid_for(B.count, 64), dim3(64), 0, s, B)
     FB_SWITCH_MVS(B.n, FB_L)
 #undef FB_L
@@ -3009,6 +3351,14 @@ hipError_t launch_plain_mvs(const Bucket &B, int waves_per_group, const StepPara
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxMvsBodies) {
+        dim3 lgrid;
+        int T, S;
+        if (!large_launch(B, 1, lgrid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_plain_mvs_large, lgrid, dim3(T), large_lds_bytes(T), s, B, P, S);
+        return hipGetLastError();
+    }
     const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
     const dim3 grid = grid_for(B.count, 64 * W);
 #define FB_L(NN) hipLaunchKernelGGL(k_plain_mvs<NN>, grid, dim3(64 * W), 0, s, B, P)
@@ -3022,6 +3372,15 @@ hipError_t launch_unpack_mvs(const Bucket &B, const long long *orig_off, double 
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxMvsBodies) {
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, 1, grid, T, S))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_unpack_mvs_large, grid, dim3(T), large_lds_bytes(T), s, B, S, orig_off,
+                           pos, vel, t, status, steps);
+        return hipGetLastError();
+    }
 #define FB_L(NN) hipLaunchKernelGGL(k_unpack_mvs<NN>, grid_for(B.count, 64), dim3(64), 0, s, B, \
                                     orig_off, pos, vel, t, status, steps)
     FB_SWITCH_MVS(B.n, FB_L)

@@ -919,10 +919,6 @@ fb_status fb_integrate_mvs(fb_ensemble *e, int64_t n_steps, double dt, const fb_
         return fail(FB_E_INVAL, "n_steps must be >= 0");
     if (!(std::isfinite(dt) && dt != 0.0))
         return fail(FB_E_INVAL, "dt must be finite and non-zero");
-    for (const Bucket &B : e->buckets)
-        if (B.n > kMaxMvsBodies)
-            return fail(FB_E_INVAL, "MVS is built for systems of at most %d bodies (got %d)",
-                        kMaxMvsBodies, B.n);
     if (n_steps == 0 || e->n_sys == 0)
         return FB_OK;
     if (!e->mvs_form()) {

@@ -173,7 +173,6 @@ def test_refusals(fb):
     E = fb.from_gen(ens)
     bad = [lambda: E.integrate_rkck_steps(10, 0.01),
            lambda: E.integrate_rkck(1.0, 0.01, 1e-9),
-           lambda: E.integrate_mvs(10, 0.01),
            lambda: E.autotune(5, 0.01)]
     for f in bad:
         with pytest.raises(fb.FewbodyError) as ei:
