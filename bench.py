@@ -238,6 +238,14 @@ def mvs_extras(fb, gen, torch, log, dt=1e-2, steps=20000):
         assert (st["status"] == fb.DONE).all()
         rows.append({"n": n, "seconds": t, "system_steps_per_s": e.n_sys * n_steps / t})
     out["paper_ics_one_time_unit"] = rows
+    # larger systems, one body per lane across a workgroup
+    for name, nsteps in (("ragged_65536x3-15", 2000), ("disk_4096x64", 1000)):
+        e, _ = gen.workload(name)
+        t, st = timed(fb, torch, e, lambda E: E.integrate_mvs(nsteps, dt))
+        done = float((st["status"] == fb.DONE).mean())
+        out[name] = {"steps": nsteps, "seconds": t, "system_steps_per_s": e.n_sys * nsteps / t,
+                     "fraction_done": done}
+        log(f"[bench] MVS {name}: {e.n_sys * nsteps / t:.3e} system-steps/s ({100 * done:.1f}% done)")
     return out
 
 

@@ -121,7 +121,9 @@ hipError_t launch_plain_rkck(const Bucket &B, int waves_per_group, const StepPar
 // read-back of a bucket in MVS form as inertial positions and velocities.
 hipError_t launch_mvs_enter(const Bucket &B, hipStream_t s);
 hipError_t launch_mvs_leave(const Bucket &B, hipStream_t s);
-hipError_t launch_plain_mvs(const Bucket &B, int waves_per_group, const StepParams &P,
+// mapping: MAP_SPL runs system per lane (n <= kMaxMvsBodies), MAP_BPL one
+// body per lane across a workgroup (any n); the two give identical results.
+hipError_t launch_plain_mvs(const Bucket &B, int mapping, int waves_per_group, const StepParams &P,
                             hipStream_t s);
 hipError_t launch_unpack_mvs(const Bucket &B, const long long *orig_off, double *pos,
                              double *vel, double *t, int *status, long long *steps,

@@ -3346,12 +3346,12 @@ hipError_t launch_mvs_leave(const Bucket &B, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_plain_mvs(const Bucket &B, int waves_per_group, const StepParams &P,
+hipError_t launch_plain_mvs(const Bucket &B, int mapping, int waves_per_group, const StepParams &P,
                             hipStream_t s)
 {
     if (B.count == 0)
         return hipSuccess;
-    if (B.n > kMaxMvsBodies) {
+    if (B.n > kMaxMvsBodies || mapping != MAP_SPL) {
         dim3 lgrid;
         int T, S;
         if (!large_launch(B, 1, lgrid, T, S))

@@ -697,7 +697,11 @@ fb_status run_mvs(fb_ensemble *e, const fb_opts &o, long long step_bound)
         for (const Bucket &B : e->buckets) {
             const StepParams P = make_params(o, quantum);
             ProfScope ps(e->stream);
-            FB_HIP(launch_plain_mvs(B, 1, P, e->stream));
+            // the Hermite plan's mapping rule (system per lane when its
+            // 64-system tiles fill the device), within MVS's own limit
+            const Plan p = B.n <= kMaxBodies ? get_plan(B.n) : Plan{MAP_BPL, 1, 0};
+            const int map = B.n > kMaxMvsBodies ? MAP_BPL : plain_mapping(p, B, false, e->num_cu);
+            FB_HIP(launch_plain_mvs(B, map, 1, P, e->stream));
         }
         if (quantum == INT_MAX)
             return FB_OK;

@@ -268,3 +268,24 @@ def test_larger_systems_diagnostics_and_unbound(fb, ora):
         e_ora, l_ora = ora.energy(ens.system(s)[0], st["pos"][sl], st["vel"][sl])
         assert abs(e_mvs[s] - e_ora) <= 1e-12 * abs(e_ora)
         assert np.abs(l_mvs[s] - l_ora).max() <= 1e-12 * np.abs(l_ora).max()
+
+
+def test_system_per_lane_and_workgroup_kernels_agree_bitwise(plans):
+    """For 2..8 bodies both MVS kernels exist; they do the same arithmetic in
+    the same order, so the mapping choice never changes a result."""
+    fb = plans
+    ens = gen.ragged_hill(300, seed=55, n_lo=2, n_hi=8)
+    dt = TWO_PI / 100
+    out = []
+    for m in (fb.MAP_SPL, fb.MAP_BPL):
+        for n in range(2, 9):
+            fb.set_plan(n, m, 2)
+        E = fb.from_gen(ens)
+        E.integrate_mvs(150, dt, fb.Opts(steps_per_quantum=40))
+        e, l = E.diagnostics()
+        out.append((E.state(), e, l))
+        E.close()
+    (a, ea, la), (b, eb, lb) = out
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    assert np.array_equal(a["status"], b["status"]) and np.array_equal(a["steps"], b["steps"])
+    assert np.array_equal(ea, eb) and np.array_equal(la, lb)
