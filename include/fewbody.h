@@ -22,7 +22,7 @@
  * both sides): Hermite steps, fixed or adaptive, with stop rules, monitors
  * and diagnostics; on the persistent schedule they run as plain launches
  * inside every quantum, beside the fused launch of the smaller systems.
- * MVS runs them too; Runge-Kutta, autotuning and the server reject
+ * MVS and Runge-Kutta run them too; autotuning and the server reject
  * ensembles holding such systems with FB_E_INVAL.
  * Flat body arrays are body-major: body b of system s is row off[s] + b with
  * off the exclusive prefix sum of n_body; pos/vel/acc/jerk rows hold x,y,z.

@@ -25,7 +25,7 @@
 #include <math.h>
 #include <stddef.h>
 
-#define ORA_RK_MAX 64
+#define ORA_RK_MAX 512
 #define ORA_ACTIVE 0
 #define ORA_DONE 1
 #define ORA_NONFINITE 4

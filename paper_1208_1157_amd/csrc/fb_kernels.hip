@@ -2974,6 +2974,160 @@ __global__ __launch_bounds__(kLargeMaxLanes) void k_unpack_mvs_large(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Runge-Kutta Cash-Karp for large systems (n > 16): one body per lane across
+// a workgroup
+// ---------------------------------------------------------------------------
+// The stages, weights and error control of k_plain_rkck in the large-n
+// layout.  Each stage's positions go to one of two LDS copies in turn, so a
+// stage costs one workgroup barrier; a body's own term is an exact zero
+// through the r^2 floor, so every lane runs the same partner loop (planets in
+// ascending order, the star last).
+
+// Acceleration of this lane's body (Eq. 1) at the stage positions xs,
+// published in copy cp.
+__device__ __forceinline__ void large_rk_accel(const LargeView &V, const int T, const int cp,
+                                               const LargeLane &l, const int n,
+                                               const double (&xs)[3], double (&acc)[3])
+{
+    double2 *xy = V.xy + cp * T, *zvx = V.zvx + cp * T;
+    xy[l.tid] = make_double2(xs[0], xs[1]);
+    zvx[l.tid] = make_double2(xs[2], 0.0);
+    __syncthreads();
+    acc[0] = acc[1] = acc[2] = 0.0;
+    if (!l.valid)
+        return;
+    for (int k = 1; k <= n; ++k) {
+        const int j = k < n ? k : 0;   // planets 1..n-1, then the star
+        const double2 p0 = xy[l.base + j], p1 = zvx[l.base + j];
+        const double rx = p0.x - xs[0], ry = p0.y - xs[1], rz = p1.x - xs[2];
+        const double ri = rsqrt_nr(fmax(fma(rz, rz, fma(ry, ry, rx * rx)), kLargeMinR2));
+        const double mr3 = V.m[l.base + j] * (ri * ri * ri);
+        acc[0] = fma(mr3, rx, acc[0]);
+        acc[1] = fma(mr3, ry, acc[1]);
+        acc[2] = fma(mr3, rz, acc[2]);
+    }
+}
+
+// Maximum of one value per lane over the lane's system, to every valid lane.
+__device__ __forceinline__ double large_sys_max(const LargeView &V, const LargeLane &l,
+                                                const int n, const double v)
+{
+    V.red[l.tid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (l.valid) {
+        r = V.red[l.base];
+        for (int b = 1; b < n; ++b)
+            r = fmax(r, V.red[l.base + b]);
+    }
+    __syncthreads();
+    return r;
+}
+
+template <bool ADV>
+__global__ __launch_bounds__(kLargeMaxLanes) void k_plain_rkck_large(Bucket B, StepParams P,
+                                                                     double eps, int S)
+{
+    using Tb = RkTableau;
+    const int T = blockDim.x, n = B.n;
+    const LargeView V = large_view(T);
+    const LargeLane l = large_lane(B, S);
+    const size_t pitch = B.pitch;
+    double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    Clock c;
+    c.status = ST_DONE;
+    if (l.valid) {
+        mi = B.st[(R_M * n + l.b) * pitch + l.slot];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            x[cc] = B.st[((R_X + cc) * n + l.b) * pitch + l.slot];
+            v[cc] = B.st[((R_V + cc) * n + l.b) * pitch + l.slot];
+        }
+        c = load_clock(B, l.slot);
+    }
+    V.m[l.tid] = mi;   // ordered before any read by the loop's first barrier
+    int cp = 0;
+    for (int q = 0; q < P.quantum; ++q) {
+        double h = 0.0;
+        bool last = false;
+        const bool act = l.valid && plan_step(c, P, h, last);
+        if (!__syncthreads_or(act))
+            break;
+        if (!act)
+            h = 0.0;
+        double kx[6][3], kv[6][3];
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            double xs[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                double dx = 0.0, dv = 0.0;
+#pragma unroll
+                for (int j = 0; j < st; ++j) {
+                    dx = fma(Tb::a[st][j], kx[j][cc], dx);
+                    dv = fma(Tb::a[st][j], kv[j][cc], dv);
+                }
+                xs[cc] = fma(h, dx, x[cc]);
+                kx[st][cc] = fma(h, dv, v[cc]);
+            }
+            large_rk_accel(V, T, cp, l, n, xs, kv[st]);
+            cp ^= 1;
+        }
+        double x5[3], v5[3], ex[3], ev[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            double sx = 0.0, sv = 0.0, ux = 0.0, uv = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                sx = fma(Tb::b[j], kx[j][cc], sx);
+                sv = fma(Tb::b[j], kv[j][cc], sv);
+                ux = fma(Tb::e[j], kx[j][cc], ux);
+                uv = fma(Tb::e[j], kv[j][cc], uv);
+            }
+            x5[cc] = fma(h, sx, x[cc]);
+            v5[cc] = fma(h, sv, v[cc]);
+            ex[cc] = h * ux;
+            ev[cc] = h * uv;
+        }
+        bool accept = true;
+        double dtp = 0.0;
+        if (ADV) {
+            const double X = large_sys_max(V, l, n, norm3d(x));
+            const double Vm = large_sys_max(V, l, n, norm3d(v));
+            const double E = large_sys_max(V, l, n, fmax(norm3d(ex) / (eps * X), norm3d(ev) / (eps * Vm)));
+            accept = E <= 1.0;
+            if (act && !accept) {
+                if (!__builtin_isfinite(E))
+                    c.status = ST_NONFINITE;
+                else
+                    c.dtn = h * fmax(0.1, 0.9 * pow(E, -0.25));
+            }
+            dtp = last ? c.dtn : h * (E > 0.0 ? fmin(5.0, fmax(0.2, 0.9 * pow(E, -0.2))) : 5.0);
+        }
+        if (act && accept) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                x[cc] = x5[cc];
+                v[cc] = v5[cc];
+            }
+            finish_step(c, P, last, h, dtp);
+        }
+    }
+    const int bad = ADV ? 0 : large_sys_or(V, l, n, (l.valid && !(finite3(x) && finite3(v))) ? 1 : 0);
+    if (!l.valid)
+        return;
+    if (bad)
+        c.status = ST_NONFINITE;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        B.st[((R_X + cc) * n + l.b) * pitch + l.slot] = x[cc];
+        B.st[((R_V + cc) * n + l.b) * pitch + l.slot] = v[cc];
+    }
+    if (l.b == 0)
+        store_clock(B, l.slot, c);
+}
+
 // FP64 issue-ceiling probe for the roofline: each lane runs kFmaChains
 // independent FMA chains (a <- a*b + c, b slightly below 1 so values stay
 // bounded), so the rate is set by VALU issue rather than FMA latency.
@@ -3422,6 +3576,19 @@ hipError_t launch_plain_rkck(const Bucket &B, int waves_per_group, const StepPar
 {
     if (B.count == 0)
         return hipSuccess;
+    if (B.n > kMaxBodies) {
+        dim3 grid;
+        int T, S;
+        if (!large_launch(B, 1, grid, T, S))
+            return hipErrorInvalidValue;
+        if (P.adaptive)
+            hipLaunchKernelGGL(k_plain_rkck_large<true>, grid, dim3(T), large_lds_bytes(T), s, B, P,
+                               eps, S);
+        else
+            hipLaunchKernelGGL(k_plain_rkck_large<false>, grid, dim3(T), large_lds_bytes(T), s, B,
+                               P, eps, S);
+        return hipGetLastError();
+    }
     const int W = waves_per_group < 1 ? 1 : (waves_per_group > 4 ? 4 : waves_per_group);
     const int S = 64 / B.n;
     const int tiles = (B.count + S - 1) / S;

@@ -1075,8 +1075,6 @@ fb_status fb_integrate_rkck_steps(fb_ensemble *e, int64_t n_steps, double dt, co
     fb_status st = check_rk_opts(o);
     if (st != FB_OK)
         return st;
-    if (has_large(e))
-        return fail(FB_E_INVAL, "Runge-Kutta runs systems of at most %d bodies", kMaxBodies);
     if (n_steps < 0)
         return fail(FB_E_INVAL, "n_steps must be >= 0");
     if (!(std::isfinite(dt) && dt != 0.0))
@@ -1104,8 +1102,6 @@ fb_status fb_integrate_rkck(fb_ensemble *e, double t_end, double dt, double eps,
     fb_status st = check_rk_opts(o);
     if (st != FB_OK)
         return st;
-    if (has_large(e))
-        return fail(FB_E_INVAL, "Runge-Kutta runs systems of at most %d bodies", kMaxBodies);
     if (!std::isfinite(t_end))
         return fail(FB_E_INVAL, "t_end must be finite");
     if (!(std::isfinite(dt) && dt > 0.0))

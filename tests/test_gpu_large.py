@@ -171,9 +171,7 @@ def test_quanta_are_bitwise_invisible(fb):
 def test_refusals(fb):
     ens = concat([gen.planetesimal_disk(2, 20, seed=91), gen.three_body(3, seed=92)])
     E = fb.from_gen(ens)
-    bad = [lambda: E.integrate_rkck_steps(10, 0.01),
-           lambda: E.integrate_rkck(1.0, 0.01, 1e-9),
-           lambda: E.autotune(5, 0.01)]
+    bad = [lambda: E.autotune(5, 0.01)]
     for f in bad:
         with pytest.raises(fb.FewbodyError) as ei:
             f()

@@ -1,5 +1,6 @@
 """The Runge-Kutta Cash-Karp kernels against the RKCK oracle: fixed-step
-parity on 2..16-body ensembles and on a sampled full-size ensemble,
+parity on 2..16-body ensembles, on 17..130-body systems (one body per lane
+across a workgroup) and on a sampled full-size ensemble,
 adaptive parity (step counts and states), bitwise independence of quanta,
 straight-line motion of massless bodies, hand-over to Hermite, and
 argument checks."""
@@ -156,3 +157,37 @@ def test_argument_checks(fb):
             f()
         assert ei.value.code == fb.E_INVAL
     E.close()
+
+
+def larger():
+    parts = [gen.planetesimal_disk(6, 17, seed=56), gen.planetesimal_disk(3, 40, seed=57),
+             gen.planetesimal_disk(2, 130, seed=58), gen.ragged_hill(20, seed=59, n_lo=3, n_hi=16)]
+    nb = np.concatenate([p.n_body for p in parts])
+    return gen.Ensemble(nb, np.concatenate([p.mass for p in parts]), np.concatenate([p.pos for p in parts]),
+                        np.concatenate([p.vel for p in parts]))
+
+
+def test_larger_systems_fixed_and_adaptive(fb, ora):
+    ens = larger()
+    dt, nsteps = TWO_PI / 200, 120
+    say("RKCK larger systems", ens.n_sys)
+    E = fb.from_gen(ens)
+    E.integrate_rkck_steps(nsteps, dt, fb.Opts(steps_per_quantum=50))
+    st = E.state()
+    E.close()
+    assert np.all(st["status"] == fb.DONE) and np.all(st["steps"] == nsteps)
+    parity(ens, st, {s: ora.integrate_rkck_fixed(*ens.system(s), dt, nsteps) for s in range(ens.n_sys)})
+    t_end, eps = 1.0, 1e-10
+    E = fb.from_gen(ens)
+    E.integrate_rkck(t_end, 0.02, eps)
+    st = E.state()
+    E.close()
+    assert np.all(st["status"] == fb.DONE) and np.all(st["t"] == t_end)
+    refs = {}
+    for s in range(ens.n_sys):
+        o = ora.integrate_rkck_adaptive(*ens.system(s), t_end, eps, 0.02)
+        assert o["status"] == ora.DONE
+        if o["steps"] == st["steps"][s]:
+            refs[s] = o
+    assert len(refs) >= 0.95 * ens.n_sys, len(refs)
+    say("adaptive worst", parity(ens, st, refs), "agree", len(refs))
