@@ -310,6 +310,30 @@ def logging_extras(fb, gen, torch, log, steps=20000, every=200):
     return out
 
 
+def table1_extras(fb, gen, torch, log, tau=1.7e-2, horizons=(0.45e6, 0.9e6, 1.3e6, 1.8e6)):
+    """Table 1's adaptive Hermite energy test: Section 5.1's three-body
+    systems (64 copies), Eq. 5 steps with step scale tau, |dE/E| at the
+    table's times (Section 5.2.2).  Minutes of GPU time; not part of
+    --extras."""
+    import numpy as np
+    ens = gen.paper_ics(64, 3)
+    E = fb.from_gen(ens)
+    e0, _ = E.diagnostics()
+    rows = []
+    t0 = time.perf_counter()
+    for T in horizons:
+        E.integrate(T, 0.0, fb.Opts(adaptive=2, eta=tau))
+        e1, _ = E.diagnostics()
+        st = E.state()
+        err = float(np.max(np.abs(e1 / e0 - 1.0)))
+        rows.append({"t": T, "steps": int(st["steps"][0]), "max_frac_energy_error": err,
+                     "seconds": time.perf_counter() - t0})
+        log(f"[bench] table1 tau={tau:g} t={T:.3g}: |dE/E| = {err:.3e}")
+    E.close()
+    return {"tau": tau, "rows": rows,
+            "paper_table1_hermite_adaptive": [2.9e-11, 6.3e-11, 9.2e-11, 14.1e-11]}
+
+
 def large_n_extras(fb, gen, torch, log):
     """The large-n gravitation (systems of 17..512 bodies, Section 4.2's
     second variant): fixed Hermite steps (dt 2pi/1000) on planetesimal disks.
@@ -372,8 +396,11 @@ def main():
                     help="also run the ragged (autotuned, plain vs persistent) and uneven-lifetimes "
                          "(plain vs compaction) comparisons")
     ap.add_argument("--extra", action="append", default=[],
-                    choices=["ragged", "lifetimes", "paper_ics", "mvs", "rkck", "large_n", "logging"],
-                    help="run only this extra workload (repeatable)")
+                    choices=["ragged", "lifetimes", "paper_ics", "mvs", "rkck", "large_n", "logging",
+                             "table1"],
+                    help="run only this extra workload (repeatable; table1 only this way)")
+    ap.add_argument("--table1-tau", type=float, default=1.7e-2,
+                    help="Eq. 5 step scale of the table1 extra (the paper's 1.7e-2)")
     ap.add_argument("--lifetimes-orbits", type=float, default=100.0,
                     help="horizon of the uneven-lifetimes extra in inner orbits (the workload's is 1e4)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
@@ -512,6 +539,8 @@ def main():
         if args.extras or name in args.extra:
             extras[name] = fn()
             restore_plans()
+    if "table1" in args.extra:
+        extras["table1"] = table1_extras(fb, gen, torch, log, tau=args.table1_tau)
     if extras:
         result["extras"] = extras
     if not args.no_cpu:
