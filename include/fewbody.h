@@ -22,8 +22,9 @@
  * both sides): Hermite steps, fixed or adaptive, with stop rules, monitors
  * and diagnostics; on the persistent schedule they run as plain launches
  * inside every quantum, beside the fused launch of the smaller systems.
- * MVS and Runge-Kutta run them too; autotuning and the server reject
- * ensembles holding such systems with FB_E_INVAL.
+ * MVS and Runge-Kutta run them too; the autotuner leaves their launch shape
+ * alone (it tunes the other buckets and the persistent launch around them);
+ * the server rejects them with FB_E_INVAL.
  * Flat body arrays are body-major: body b of system s is row off[s] + b with
  * off the exclusive prefix sum of n_body; pos/vel/acc/jerk rows hold x,y,z.
  * All floating point is IEEE binary64.

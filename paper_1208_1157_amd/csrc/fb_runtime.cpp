@@ -1309,8 +1309,6 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         *n_out = 0;
     if (e->n_sys == 0)
         return FB_OK;
-    if (has_large(e))
-        return fail(FB_E_INVAL, "autotuning covers systems of at most %d bodies", kMaxBodies);
     fb_status st0 = ensure_inertial(e);
     if (st0 != FB_OK)
         return st0;
@@ -1332,8 +1330,11 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         fb_opts o;
         fb_opts_default(&o);
         P = make_params(o, INT_MAX);
-        // plain schedule: per bucket, mapping x waves per group
+        // plain schedule: per bucket, mapping x waves per group (the large-n
+        // buckets have a fixed launch shape and no plan to tune)
         for (const Bucket &B : e->buckets) {
+            if (B.n > kMaxBodies)
+                continue;
             struct Cand { int map, W; };
             std::vector<Cand> cands;
             for (int W : {1, 2, 4}) {

@@ -168,15 +168,13 @@ def test_quanta_are_bitwise_invisible(fb):
     assert np.array_equal(out[0]["pos"], out[1]["pos"]) and np.array_equal(out[0]["vel"], out[1]["vel"])
 
 
-def test_refusals(fb):
+def test_autotune_and_server(plans):
+    fb = plans
     ens = concat([gen.planetesimal_disk(2, 20, seed=91), gen.three_body(3, seed=92)])
     E = fb.from_gen(ens)
-    bad = [lambda: E.autotune(5, 0.01)]
-    for f in bad:
-        with pytest.raises(fb.FewbodyError) as ei:
-            f()
-        assert ei.value.code == fb.E_INVAL
-    assert np.all(E.state()["steps"] == 0)
+    entries = E.autotune(5, 0.01)                 # tunes the small bucket and the fused launch only
+    assert entries and all(e["n"] <= 16 for e in entries)
+    assert np.all(E.state()["steps"] == 0)          # state restored after tuning
     E.close()
     with fb.Server() as S:
         with pytest.raises(fb.FewbodyError) as ei:
