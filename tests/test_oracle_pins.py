@@ -518,3 +518,76 @@ def test_paper_rule_adaptive_run_two_body(ora):
     xe, _ = kepler.two_body_state(m0, m1, a, e, T)
     assert out["status"] == ora.DONE and out["t"] == T
     assert np.abs(out["pos"] - xe).max() < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Table 1 (Section 5.2.2): long-run energy error on Section 5.1's system.
+# The printed values live in tests/golden/table1_energy_error.txt.  They are
+# not reproduced in magnitude at the printed step parameters (the tests bound
+# the gap); what the table shows and the oracle must share is the shape of
+# the error in time: a linear drift for adaptive Hermite, a bounded error for
+# the symplectic MVS.
+# --------------------------------------------------------------------------
+def _table1():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_energy_error.txt")
+    rows = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, t, err = line.split()
+                rows.setdefault(name, []).append((float(t), float(err)))
+    return {k: np.array(v) for k, v in rows.items()}
+
+
+def _section51_system():
+    from paper_1208_1157_amd import gen
+    m, x, v = gen.paper_ics(1, 3).system(0)
+    assert m[0] == 1.0 and np.all(m[1:] == 1e-3)
+    return m, x, v
+
+
+def test_table1_hermite_drift_is_linear(ora):
+    """Eq. 5 at the printed dtau = 1.7e-2, over 1/20 of the table's times:
+    the error grows in proportion to time, as the table's does (its rates per
+    time unit agree within 10%).  The oracle's rate is 30-40x the table's
+    (the reading that leaves Table 1 unreproduced); the bound catches a change
+    of the Eq. 5 reading or of the integrator's order."""
+    tab = _table1()["hermite"]
+    rate_tab = tab[:, 1] / tab[:, 0]
+    assert np.all(np.abs(rate_tab / rate_tab.mean() - 1) < 0.15)
+    m, x, v = _section51_system()
+    e0 = ora.energy(m, x, v)[0]
+    st = dict(pos=x, vel=v, acc=None, jerk=None, dt_next=None, steps=0, t=0.0)
+    errs = []
+    for T in tab[:, 0] / 20:
+        st = ora.integrate_adaptive(m, st["pos"], st["vel"], T, eta=1.7e-2, stop_rules=0,
+                                    paper_rule=True, t0=st["t"], acc=st["acc"], jerk=st["jerk"],
+                                    dt_next=st["dt_next"], steps=st["steps"])
+        assert st["status"] == ora.DONE and st["t"] == T
+        errs.append(ora.energy(m, st["pos"], st["vel"])[0] / e0 - 1)
+    errs = np.array(errs)
+    assert np.all(errs > 0) or np.all(errs < 0)
+    rate = np.abs(errs) / (tab[:, 0] / 20)
+    assert np.all(np.abs(rate / rate.mean() - 1) < 0.15), rate
+    assert 10 < rate.mean() / rate_tab.mean() < 100, (rate.mean(), rate_tab.mean())
+
+
+def test_table1_mvs_error_is_bounded(ora):
+    """MVS at the printed dt = 1e-2, over 1/100 of the table's times: like the
+    table's row, the error does not grow with time.  Its size, ~4e-8, is that
+    of a symplectic map's error here, (m_planet/m_star) (w dt)^2 = 1e-7 with
+    w = 1, and far above the printed 5e-11: the table is not reproduced in
+    magnitude."""
+    tab = _table1()["mvs"]
+    assert tab[:, 1].max() < 1.1 * tab[:, 1].min()
+    m, x, v = _section51_system()
+    e0 = ora.energy(m, x, v)[0]
+    errs, t = [], 0.0
+    for T in tab[:, 0] / 100:
+        n = int(round((T - t) / 1e-2))
+        out = ora.integrate_mvs(m, x, v, 1e-2, n)
+        assert out["steps"] == n
+        x, v, t = out["pos"], out["vel"], t + n * 1e-2
+        errs.append(abs(ora.energy(m, x, v)[0] / e0 - 1))
+    assert max(errs) < 1e-7 and errs[-1] < 2 * max(errs[:-1]), errs
