@@ -357,7 +357,7 @@ def large_n_extras(fb, gen, torch, log):
 
 
 def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, policy="srpt",
-                   cls="spl", quantum_tiles=0, long_steps=300000):
+                   cls="spl", quantum_tiles=0, long_steps=300000, idle_spread=0):
     from paper_1208_1157_amd import serve
     trace = gen.serving_trace(n_req, rate=200.0, seed=4)
     saved = fb.get_plan(0)
@@ -365,7 +365,8 @@ def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, po
     try:
         rep = serve.run_trace(fb, trace, max_resident=max_resident, steps_per_quantum=quantum, log=log,
                               policy=fb.POLICY_SRPT if policy == "srpt" else fb.POLICY_FAIR,
-                              quantum_tiles=quantum_tiles, long_steps=long_steps)
+                              quantum_tiles=quantum_tiles, long_steps=long_steps,
+                              idle_spread=idle_spread)
     finally:
         fb.set_plan(0, *saved)
     rep["max_resident"] = max_resident
@@ -374,6 +375,7 @@ def serving_report(fb, gen, log, n_req=2000, max_resident=4096, quantum=2000, po
     rep["fused_class"] = "system-per-lane" if cls == "spl" else "body-per-lane"
     rep["quantum_tiles"] = quantum_tiles
     rep["long_steps"] = long_steps
+    rep["idle_spread"] = idle_spread >= 0
     rep["workload"] = (f"serving: {n_req} requests, Poisson 200 req/s, 1..4096 systems (log-uniform) of 3..10 "
                        f"bodies, t_end 2pi*10^U(1,3), dt 2pi/1000")
     lat = {"n3_system_per_lane": step_latency(fb, gen, 3, fb.MAP_SPL),

@@ -390,6 +390,12 @@ typedef struct {
     int32_t long_steps;         /* SRPT: requests with at least this many steps left
                                    run in every quantum, whatever their work, since
                                    their step count alone sets their latency (0: none) */
+    int32_t idle_spread;        /* system-per-lane class: while a quantum's slowest
+                                   tiles, not its total work, set its length, the
+                                   slowest system-per-lane tiles run body-per-lane
+                                   instead (a system over n lanes): shorter quanta
+                                   under light load, bitwise the same results
+                                   (0 or 1: on; -1: off)                            */
 } fb_server_opts;
 
 typedef struct {
@@ -397,6 +403,8 @@ typedef struct {
     double system_steps;        /* Hermite system-steps executed                    */
     double busy_seconds;        /* wall time spent inside quanta                    */
     size_t bytes_in_use, peak_bytes;
+    int64_t spread_quanta;      /* quanta in which idle_spread moved system-per-lane
+                                   tiles to body-per-lane                           */
 } fb_server_stats;
 
 void fb_server_opts_default(fb_server_opts *o);

@@ -247,11 +247,14 @@ long long schedule_steps(double t0, double t_end, double dt)
 
 double flops_per_system_step(int n) { return 116.0 * n * (n - 1) / 2 + 120.0 * n; }
 
-// Relative duration of one step of a tile: a system-per-lane lane walks all
-// n(n-1)/2 pairs, a body-per-lane lane its n-1 partners.
+// Relative duration of one step of a tile, in units of one pair: a
+// system-per-lane lane walks all n(n-1)/2 pairs, a body-per-lane lane its
+// n-1 partners.  The per-body and per-lane overheads are fitted to single-tile
+// step times (3 and 10 bodies per lane: 0.69 and 9.3 us; 10 bodies, one body
+// per lane: 2.4 us).
 double tile_step_cost(int map, int n)
 {
-    return map == MAP_SPL ? 0.5 * n * (n - 1) + n : (double)n;
+    return map == MAP_SPL ? 0.5 * n * (n - 1) + 0.15 * n : 1.2 * n;
 }
 
 // Device bytes a request needs on an empty server.
@@ -512,8 +515,10 @@ int server_mapping(const fb_server *S, int n)
 
 // One quantum.  Returns the requests it finished (reached their step count
 // or were cancelled).
-fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sys_steps)
+fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sys_steps,
+                      bool &spread)
 {
+    spread = false;
     const int Q = S->opts.steps_per_quantum;
     sys_steps = 0.0;
     const int cls = S->cls, W = S->waves_per_group, gpc = S->groups_per_cu;
@@ -589,6 +594,76 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
             return a.adv > b.adv;
         return a.first < b.first;
     });
+    // One group of runs per chunk, with the mapping its tiles use.
+    struct Group {
+        size_t begin, end;
+        int n, map;
+        long long len, adv;   // systems; the most steps any of them takes this quantum
+    };
+    std::vector<Group> groups;
+    for (size_t i = 0; i < runs.size();) {
+        Group g{i, i, runs[i].c->n, server_mapping(S, runs[i].c->n), 0, runs[i].adv};
+        for (; i < runs.size() && runs[i].c == runs[g.begin].c; ++i)
+            g.len += runs[i].count;
+        g.end = i;
+        groups.push_back(g);
+    }
+    // A quantum lasts about as long as its slowest tile, or as its work spread
+    // evenly over the resident waves if that is longer.  While it is the
+    // slowest tile that sets the bound, the group with the slowest
+    // system-per-lane tiles moves to body-per-lane tiles (n lanes per system,
+    // each walking n-1 partners: more work, several times less time per
+    // step), slowest first, as far as that lowers the bound.  A loaded quantum
+    // keeps its mapping; a light one (a trace's tail, few requests) gets
+    // shorter.  Both mappings give bitwise the same states, so a request's
+    // results do not depend on it.
+    const double resident_waves = (double)gpc * W * S->num_cu;
+    if (cls == 1 && S->opts.idle_spread >= 0) {
+        auto tiles = [&](const Group &G, int map) {
+            const int cap = tile_systems(map, G.n);
+            return (double)((G.len + cap - 1) / cap);
+        };
+        auto cost = [&](const Group &G, int map) {
+            return (double)G.adv * tile_step_cost(map, G.n);
+        };
+        double work = 0.0, slow_bpl = 0.0;
+        std::vector<size_t> order;
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const Group &G = groups[g];
+            work += tiles(G, G.map) * cost(G, G.map);
+            if (G.map == MAP_SPL)
+                order.push_back(g);
+            else
+                slow_bpl = std::max(slow_bpl, cost(G, MAP_BPL));
+        }
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+            return cost(groups[a], MAP_SPL) > cost(groups[b], MAP_SPL);
+        });
+        // The prefix of `order` to move is the one with the lowest bound
+        // (groups of equal cost only pay off together), if it gains at least
+        // 5%: the extra work would otherwise be spent for little.
+        auto bound = [&](double slowest, double w) { return std::max(slowest, w / resident_waves); };
+        const size_t m = order.size();
+        const double bound0 = bound(std::max(m ? cost(groups[order[0]], MAP_SPL) : 0.0, slow_bpl), work);
+        double best = bound0;
+        size_t best_k = 0;
+        for (size_t k = 0; k < m; ++k) {
+            const Group &G = groups[order[k]];
+            work += tiles(G, MAP_BPL) * cost(G, MAP_BPL) - tiles(G, MAP_SPL) * cost(G, MAP_SPL);
+            slow_bpl = std::max(slow_bpl, cost(G, MAP_BPL));
+            const double next = k + 1 < m ? cost(groups[order[k + 1]], MAP_SPL) : 0.0;
+            const double b = bound(std::max(next, slow_bpl), work);
+            if (b < best) {
+                best = b;
+                best_k = k + 1;
+            }
+        }
+        if (best > 0.95 * bound0)
+            best_k = 0;
+        for (size_t k = 0; k < best_k; ++k)
+            groups[order[k]].map = MAP_BPL;
+        spread = best_k > 0;
+    }
     struct Item {
         Tile t;
         double cost;
@@ -596,16 +671,16 @@ fb_status run_quantum(fb_server *S, std::vector<Request *> &finished, double &sy
     std::vector<Item> items;
     S->h_buckets.clear();
     S->h_list.clear();
-    for (size_t i = 0; i < runs.size();) {
-        Chunk *c = runs[i].c;
-        const int n = c->n;
-        const int map = server_mapping(S, n);
+    for (const Group &G : groups) {
+        Chunk *c = runs[G.begin].c;
+        const int n = G.n;
+        const int map = G.map;
         const int cap = tile_systems(map, n);
         const int bi = (int)S->h_buckets.size();
         S->h_buckets.push_back(c->B);
         const size_t list0 = S->h_list.size();
         std::vector<long long> adv_of;
-        for (; i < runs.size() && runs[i].c == c; ++i)
+        for (size_t i = G.begin; i < G.end; ++i)
             for (int k = 0; k < runs[i].count; ++k) {
                 S->h_list.push_back(runs[i].first + k);
                 adv_of.push_back(runs[i].adv);
@@ -714,6 +789,7 @@ void worker_main(fb_server *S)
         }
         std::vector<Request *> finished;
         double sys_steps = 0.0, t0 = now_s(), t1 = t0;
+        bool spread = false;
         if (err == FB_OK) {
             std::lock_guard<std::mutex> lk(S->mu);
             const double ta = now_s();
@@ -726,7 +802,7 @@ void worker_main(fb_server *S)
         }
         if (err == FB_OK && !S->resident.empty()) {
             t0 = now_s();
-            err = run_quantum(S, finished, sys_steps);
+            err = run_quantum(S, finished, sys_steps, spread);
             t1 = now_s();
         }
         std::lock_guard<std::mutex> lk(S->mu);
@@ -745,6 +821,7 @@ void worker_main(fb_server *S)
             S->st.quanta++;
             S->st.busy_seconds += t1 - t0;
             S->st.system_steps += sys_steps;
+            S->st.spread_quanta += spread ? 1 : 0;
         }
         const double td = now_s();
         for (Request *R : finished) {
@@ -784,6 +861,7 @@ fb_status resolve_opts(const fb_server_opts *po, fb_server_opts &o)
         o.policy = po->policy;
         o.quantum_tiles = po->quantum_tiles;
         o.long_steps = po->long_steps;
+        o.idle_spread = po->idle_spread;
         if (po->chunk_slots)
             o.chunk_slots = po->chunk_slots;
     }
@@ -793,6 +871,8 @@ fb_status resolve_opts(const fb_server_opts *po, fb_server_opts &o)
         return fail(FB_E_INVAL, "policy must be FB_POLICY_FAIR or FB_POLICY_SRPT");
     if (o.quantum_tiles < 0 || o.long_steps < 0)
         return fail(FB_E_INVAL, "quantum_tiles and long_steps must be >= 0");
+    if (o.idle_spread < -1 || o.idle_spread > 1)
+        return fail(FB_E_INVAL, "idle_spread must be -1, 0 or 1");
     if (o.chunk_slots < 64 || o.chunk_slots > (1 << 20) || o.chunk_slots % 64)
         return fail(FB_E_INVAL, "chunk_slots must be a multiple of 64 in 64..2^20");
     return FB_OK;

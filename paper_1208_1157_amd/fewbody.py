@@ -50,7 +50,7 @@ class FbServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_resident", ctypes.c_int32),
                 ("steps_per_quantum", ctypes.c_int32), ("policy", ctypes.c_int32),
                 ("quantum_tiles", ctypes.c_int32), ("chunk_slots", ctypes.c_int32),
-                ("long_steps", ctypes.c_int32)]
+                ("long_steps", ctypes.c_int32), ("idle_spread", ctypes.c_int32)]
 
 
 class FbServerStats(ctypes.Structure):
@@ -58,7 +58,8 @@ class FbServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("resident", ctypes.c_int64), ("quanta", ctypes.c_int64),
                 ("system_steps", ctypes.c_double), ("busy_seconds", ctypes.c_double),
-                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("spread_quanta", ctypes.c_int64)]
 
 
 class FbLogSpec(ctypes.Structure):
@@ -421,9 +422,9 @@ def monotonic() -> float:
 
 
 def server_opts(budget_bytes=0, max_resident=0, steps_per_quantum=0, policy=POLICY_FAIR,
-                quantum_tiles=0, chunk_slots=0, long_steps=0) -> FbServerOpts:
+                quantum_tiles=0, chunk_slots=0, long_steps=0, idle_spread=0) -> FbServerOpts:
     return FbServerOpts(int(budget_bytes), int(max_resident), int(steps_per_quantum), int(policy),
-                        int(quantum_tiles), int(chunk_slots), int(long_steps))
+                        int(quantum_tiles), int(chunk_slots), int(long_steps), int(idle_spread))
 
 
 def server_request_bytes(n_body, **opts) -> int:
@@ -442,9 +443,9 @@ class Server:
     retires finished requests."""
 
     def __init__(self, budget_bytes=0, max_resident=0, steps_per_quantum=0, stream=None,
-                 policy=POLICY_FAIR, quantum_tiles=0, chunk_slots=0, long_steps=0):
+                 policy=POLICY_FAIR, quantum_tiles=0, chunk_slots=0, long_steps=0, idle_spread=0):
         o = server_opts(budget_bytes, max_resident, steps_per_quantum, policy, quantum_tiles,
-                        chunk_slots, long_steps)
+                        chunk_slots, long_steps, idle_spread)
         self._h = ctypes.c_void_p()
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(_lib.fb_server_create(ctypes.byref(o), sp, ctypes.byref(self._h)))

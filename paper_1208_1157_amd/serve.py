@@ -35,10 +35,11 @@ def request_steps(t_end, dt):
 
 
 def run_trace(fb, trace, budget_bytes=0, max_resident=0, steps_per_quantum=0, keep_results=False,
-              log=None, policy=0, quantum_tiles=0, chunk_slots=0, long_steps=0):
+              log=None, policy=0, quantum_tiles=0, chunk_slots=0, long_steps=0, idle_spread=0):
     """Replay `trace` (list of gen.Request) in real time; returns a report dict."""
     srv = fb.Server(budget_bytes, max_resident, steps_per_quantum, policy=policy,
-                    quantum_tiles=quantum_tiles, chunk_slots=chunk_slots, long_steps=long_steps)
+                    quantum_tiles=quantum_tiles, chunk_slots=chunk_slots, long_steps=long_steps,
+                    idle_spread=idle_spread)
     try:
         t0 = fb.monotonic()
         ids = []
@@ -81,6 +82,7 @@ def run_trace(fb, trace, budget_bytes=0, max_resident=0, steps_per_quantum=0, ke
         "aggregate_system_steps_per_s": steps_total / makespan if makespan > 0 else float("nan"),
         "offered_system_steps_per_s": offered,
         "quanta": stats["quanta"],
+        "spread_quanta": stats["spread_quanta"],
         "busy_fraction": stats["busy_seconds"] / makespan if makespan > 0 else float("nan"),
         "peak_device_bytes": stats["peak_bytes"],
     }

@@ -37,5 +37,8 @@ int main(void)
     fb_server_opts_default(&so);
     printf("server_request_ok %d\n", fb_server_request_bytes(&so, 2, nb_ok) > 0);
     printf("server_request_large %zu\n", fb_server_request_bytes(&so, 3, nb_ok));
+    so.idle_spread = 5;
+    printf("server_bad_spread %zu\n", fb_server_request_bytes(&so, 2, nb_ok));
+    printf("sizes %zu %zu\n", sizeof(fb_server_opts), sizeof(fb_server_stats));
     return 0;
 }

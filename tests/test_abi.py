@@ -118,7 +118,7 @@ def test_product_path_does_not_touch_the_oracle():
 def test_server_request_bytes(fbmod):
     """Host-only accounting: a staging block plus whole pool chunks per body
     count; invalid counts or options give 0."""
-    assert ctypes.sizeof(fbmod.FbServerOpts) == 32
+    assert ctypes.sizeof(fbmod.FbServerOpts) == 40
     one = fbmod.server_request_bytes([5], chunk_slots=64)
     full = fbmod.server_request_bytes([5] * 64, chunk_slots=64)
     two_chunks = fbmod.server_request_bytes([5] * 65, chunk_slots=64)
@@ -131,6 +131,8 @@ def test_server_request_bytes(fbmod):
     assert fbmod.server_request_bytes([5], chunk_slots=100) == 0  # not a multiple of 64
     assert fbmod.server_request_bytes([5], policy=7) == 0
     assert fbmod.server_request_bytes([5], long_steps=-1) == 0
+    assert fbmod.server_request_bytes([5], idle_spread=2) == 0
+    assert fbmod.server_request_bytes([5], chunk_slots=64, idle_spread=-1) == one
     assert fbmod.server_request_bytes([]) > 0
 
 

@@ -1,6 +1,7 @@
 """The C ABI used from C and C++ programs (no GPU): include/fewbody.h
 compiles as C99 and as C++17 with warnings as errors, links against
 libfewbody.so, and the host-side calls behave as documented."""
+import ctypes
 import os
 import shutil
 import subprocess
@@ -39,3 +40,8 @@ def test_header_compiles_links_and_validates(tmp_path, compiler, std, lang):
     assert r["create_bad_n"] == "-1 1"
     assert r["server_request_ok"] == "1"
     assert r["server_request_large"] == "0"      # the server takes at most 16 bodies per system
+    assert r["server_bad_spread"] == "0"
+    # the C structs and the binding's ctypes mirrors agree
+    from paper_1208_1157_amd import fewbody as fbmod
+    assert r["sizes"].split() == [str(ctypes.sizeof(fbmod.FbServerOpts)),
+                                  str(ctypes.sizeof(fbmod.FbServerStats))]

@@ -375,11 +375,43 @@ def test_paper_step_rule_parity(plans, ora, mapping):
         assert st["t"][s] == t_end
 
 
+@pytest.mark.parametrize("mode", ["fixed", "pairwise", "eq5"])
+def test_spl_and_bpl_agree_bitwise(plans, mode):
+    """The two lane mappings compute the same expressions in the same order
+    (each pair's terms are exact negations from the two sides; every body sums
+    its planets in ascending order and the star last), so they give bitwise
+    the same states, step counts and times.  The server relies on this when it
+    moves tiles between mappings."""
+    fb = plans
+    ens = gen.ragged_hill(3000, seed=11, n_lo=2, n_hi=10)
+    out = []
+    for mapping in (fb.MAP_SPL, fb.MAP_BPL):
+        for n in range(2, 11):
+            fb.set_plan(n, mapping, 2, 0)
+        say("spl vs bpl", mode, mapping)
+        E = fb.from_gen(ens)
+        if mode == "fixed":
+            E.integrate_steps(300, H1000)
+        else:
+            E.integrate(2 * math.pi * 3, 0.0, fb.Opts(adaptive=1 if mode == "pairwise" else 2,
+                                                      eta=0.01 if mode == "pairwise" else 1.7e-2,
+                                                      stop_rules=3 if mode == "pairwise" else 0))
+        st = E.state()
+        acc, jerk, _ = E.hermite_state()
+        E.close()
+        out.append((st, acc, jerk))
+    (a, aa, aj), (b, ba, bj) = out
+    for k in ("pos", "vel", "t", "steps", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(aa, ba) and np.array_equal(aj, bj)
+
+
 def test_auto_mapping_matches_the_explicit_launch(plans):
     """FB_MAP_AUTO resolves per bucket: system-per-lane for a bucket that
     gives every SIMD a wavefront, body-per-lane for a small one; results are
-    bit-identical to the explicitly planned launch (and differ from the other
-    mapping wherever the two mappings round differently)."""
+    bit-identical to the explicitly planned launch.  (The two mappings agree
+    bitwise as well, so this checks that the auto launches of a large and a
+    small bucket run and match, not which mapping they picked.)"""
     fb = plans
     big = gen.ragged_hill(65536, seed=5, n_lo=6, n_hi=6)
     small = gen.ragged_hill(700, seed=6, n_lo=6, n_hi=6)
@@ -392,8 +424,7 @@ def test_auto_mapping_matches_the_explicit_launch(plans):
         fb.set_plan(6, other, 2, 0)
         c, _, _ = run_gpu(fb, ens, 40, H2000)
         assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
-        if not np.array_equal(b["pos"], c["pos"]):
-            assert not np.array_equal(a["pos"], c["pos"])
+        assert np.array_equal(a["pos"], c["pos"]) and np.array_equal(a["vel"], c["vel"])
 
 
 def test_fp64_fma_ceiling(fb):

@@ -74,6 +74,29 @@ def test_results_identical_alone_and_in_the_mix(plans, ora, cls, policy):
         assert_parity(ens.n_body, mixed[k]["pos"], mixed[k]["vel"], X, V, label="serving vs oracle")
 
 
+def test_idle_spread_is_bitwise_neutral(plans):
+    """System-per-lane class: on a lightly loaded server the slowest
+    system-per-lane tiles run body-per-lane (idle_spread); every request's
+    results are bitwise those of a server that never spreads."""
+    fb = plans
+    fb.set_plan(0, fb.MAP_SPL, 2, 8)
+    reqs = small_requests(6, seed=7, max_sys=200, orbits=(0.5, 1.5))
+    res = {}
+    for spread in (-1, 1):
+        say("idle spread", spread)
+        with fb.Server(steps_per_quantum=250, chunk_slots=64, idle_spread=spread) as srv:
+            ids = [srv.submit_gen(e, t, H) for e, t in reqs]
+            out = []
+            for rid in ids:
+                assert srv.wait(rid, 120.0) == fb.REQ_DONE
+                out.append(srv.result(rid))
+            res[spread] = (out, srv.stats()["spread_quanta"])
+    assert res[-1][1] == 0 and res[1][1] > 0
+    for k, (off, on) in enumerate(zip(res[-1][0], res[1][0])):
+        for key in ("pos", "vel", "t", "steps", "status"):
+            assert np.array_equal(off[key], on[key]), (k, key)
+
+
 def test_admission_by_memory_budget(fb):
     """Requests that each fill a pool chunk cannot share one: with room for a
     single request, each waits until the one before it finishes."""
