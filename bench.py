@@ -417,12 +417,14 @@ def main():
                     help="SRPT tiles per quantum (0: the server's default)")
     ap.add_argument("--serve-long-steps", type=int, default=300000,
                     help="SRPT: requests with at least this many steps left run every quantum")
+    ap.add_argument("--serve-no-idle-spread", action="store_true",
+                    help="keep every system-per-lane tile in its mapping, however light the load")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (this path shards by system; --gpus {args.gpus} "
-              "is not supported in this build)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the path would "
+              "shard by system across GPUs, which is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -524,7 +526,7 @@ def main():
     if not args.no_serve:
         rep = serving_report(fb, gen, log, args.serve_requests, args.serve_max_resident, args.serve_quantum,
                              args.serve_policy, args.serve_class, args.serve_quantum_tiles,
-                             args.serve_long_steps)
+                             args.serve_long_steps, -1 if args.serve_no_idle_spread else 0)
         result["p50_latency_s"] = rep["p50_latency_s"]
         result["p99_latency_s"] = rep["p99_latency_s"]
         extras["serving"] = rep
