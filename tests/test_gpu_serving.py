@@ -81,6 +81,8 @@ def test_idle_spread_is_bitwise_neutral(plans):
     fb = plans
     fb.set_plan(0, fb.MAP_SPL, 2, 8)
     reqs = small_requests(6, seed=7, max_sys=200, orbits=(0.5, 1.5))
+    # and systems the class always runs body-per-lane (11..16 bodies)
+    reqs.append((gen.ragged_hill(90, seed=8, n_lo=11, n_hi=16), 2 * math.pi * 0.7))
     res = {}
     for spread in (-1, 1):
         say("idle spread", spread)
