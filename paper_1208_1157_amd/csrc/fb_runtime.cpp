@@ -1385,7 +1385,12 @@ fb_status fb_autotune(fb_ensemble *e, int64_t steps, double dt, fb_tune_entry *o
         for (int cls : {0, 1})
         for (int W : {1, 2, 4}) {
             const int occ = persistent_max_groups_per_cu(0, cls, W);
-            for (int g : {1, 2, 4, 8, 16, 32}) {
+            // powers of two, and the most groups that fit a CU at once
+            std::vector<int> counts = {1, 2, 4, 8, 16, 32};
+            if (occ > 0 && std::find(counts.begin(), counts.end(), occ) == counts.end())
+                counts.push_back(occ);
+            std::sort(counts.begin(), counts.end());
+            for (int g : counts) {
                 if (occ > 0 && g > occ)
                     continue;
                 const int cmap = cls ? FB_MAP_SYSTEM_PER_LANE : FB_MAP_BODY_PER_LANE;
