@@ -48,7 +48,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1208_1157_amd", "csrc", "fb_kernels.hip")
 MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596.1,
                     "1c9dff3d544099cf": 92417308.4, "234f298587126ea3": 92405022.4,
                     "b0cf1370d8600140": 92417213.2, "d75718a170f1a208": 92400808.0,
-                    "2e972ba6903455f7": 92417165.5, "b18c3be0358ab8a1": 92417237.0}
+                    "2e972ba6903455f7": 92417165.5, "b18c3be0358ab8a1": 92417237.0,
+                    "1ed17940f99ee27b": 92404903.3}
 # Hardware counters of the same kernel on this workload (profiles/), keyed the
 # same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
 # lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
@@ -66,6 +67,8 @@ MEASURED_COUNTERS = {
                          "shader_clock_ghz": 1.94, "valu_insts_per_system_step": 388.01},
     "b18c3be0358ab8a1": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9708,
                          "shader_clock_ghz": 2.025, "valu_insts_per_system_step": 388.01},
+    "1ed17940f99ee27b": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9677,
+                         "shader_clock_ghz": 1.939, "valu_insts_per_system_step": 388.01},
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 # Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
