@@ -99,6 +99,29 @@ def test_idle_spread_is_bitwise_neutral(plans):
             assert np.array_equal(off[key], on[key]), (k, key)
 
 
+def test_idle_spread_shortens_a_lone_request(plans):
+    """A lone request of 10-body systems on an idle server: with idle spread
+    its quanta run body-per-lane tiles, several times shorter per step (the
+    single-tile step times are 9.3 us and 2.4 us), so it finishes well
+    before the same request without it."""
+    fb = plans
+    fb.set_plan(0, fb.MAP_SPL, 2, 8)
+    ens = gen.ragged_hill(256, seed=23, n_lo=10, n_hi=10)
+    lat = {}
+    for spread in (-1, 1):
+        say("lone request, idle spread", spread)
+        with fb.Server(steps_per_quantum=2000, idle_spread=spread) as srv:
+            warm = srv.submit_gen(ens, 2 * math.pi * 2, H)    # first-launch costs
+            assert srv.wait(warm, 120.0) == fb.REQ_DONE
+            srv.result(warm)
+            rid = srv.submit_gen(ens, 2 * math.pi * 30, H)    # 30000 steps, 15 quanta
+            assert srv.wait(rid, 120.0) == fb.REQ_DONE
+            r = srv.result(rid)
+            lat[spread] = r["t_done"] - r["t_submit"]
+    say("latency without / with idle spread", lat[-1], lat[1])
+    assert lat[1] < 0.7 * lat[-1], lat
+
+
 def test_admission_by_memory_budget(fb):
     """Requests that each fill a pool chunk cannot share one: with room for a
     single request, each waits until the one before it finishes."""
