@@ -2,13 +2,13 @@
 
 Each mutant is a plausible slip (a misread coefficient, a dropped power of
 h, a wrong sign, a swapped mass index, a double-counted pair, the star added
-first; for MVS a wrong Kepler mu, a dropped or reversed reflex drift, a
-whole kick, the star in the kick, a wrong f function, a wrong mass; for
-Cash-Karp a misread tableau entry, stale stage velocities, a loose
-acceptance test).  The
-copy is compiled into a temporary library and the pin suite of the mutated
-source is run against it in a subprocess; every mutant must make at least
-one pin fail, and the unmutated copy must pass.
+first, a misread stop rule, stall threshold or step cap; for MVS a wrong
+Kepler mu, a dropped or reversed reflex drift, a whole kick, the star in the
+kick, a wrong f function, a wrong mass; for Cash-Karp a misread tableau
+entry, stale stage velocities, a loose acceptance test).  The copy is
+compiled into a temporary library and the pin suite of the mutated source is
+run against it in a subprocess; every mutant must make at least one pin
+fail, and the unmutated copy must pass.
 """
 import os
 import subprocess
@@ -45,6 +45,23 @@ MUTANTS = {
     "timestep_radial_factor": ("hermite",
                                "J[c] = mu * (u[c] / (r2 * rn) - 3.0 * ru * r[c] / (r2 * r2 * rn));",
                                "J[c] = mu * (u[c] / (r2 * rn) - 2.0 * ru * r[c] / (r2 * r2 * rn));"),
+    # Stop rules: the Hill radius without its factor 3 or without m0, or from
+    # one planet's distance alone; distances from the origin instead of the
+    # star (for both rules, or for the ejection test only); only adjacent
+    # planet pairs tested; a stall threshold ten times too high; one step
+    # too many before MAXSTEPS.
+    "hill_factor_3": ("hermite", "cbrt((m[i] + m[j]) / (3.0 * m[0]))", "cbrt((m[i] + m[j]) / m[0])"),
+    "hill_star_mass": ("hermite", "cbrt((m[i] + m[j]) / (3.0 * m[0]))", "cbrt((m[i] + m[j]) / 3.0)"),
+    "hill_one_distance": ("hermite", "0.5 * (rs[i] + rs[j])", "rs[i]"),
+    "distance_from_origin": ("hermite", "d[c] = x[3 * i + c] - x[c];", "d[c] = x[3 * i + c];"),
+    "eject_from_origin": ("hermite", "if (rs[i] > r_eject)",
+                          "if (sqrt(x[3 * i] * x[3 * i] + x[3 * i + 1] * x[3 * i + 1] + "
+                          "x[3 * i + 2] * x[3 * i + 2]) > r_eject)"),
+    "encounter_adjacent_pairs_only": ("hermite",
+                                      "for (int j = i + 1; j < n; ++j) {\n                double d[3];",
+                                      "for (int j = i + 1; j < n && j < i + 2; ++j) {\n                double d[3];"),
+    "stall_threshold": ("hermite", "!(*dt_next >= 1e-12 * fabs(t_end))", "!(*dt_next >= 1e-11 * fabs(t_end))"),
+    "max_steps_off_by_one": ("hermite", "if (*steps >= max_steps) {", "if (*steps > max_steps) {"),
     # MVS: the two-body mu of Jacobi-style splittings, a dropped or reversed
     # reflex drift, a whole kick where half belongs, the star in the kick, a
     # wrong f function and the wrong mass in the star's velocity.

@@ -435,6 +435,206 @@ def test_stop_rules(ora):
     assert ora.check_stop(m, x4, v, 3, 100.0) == ora.NONFINITE
 
 
+# The stop rules as their definitions read, probed on both sides of each
+# threshold in frames where a plausible slip changes the answer: the star
+# displaced from the origin and moving, a star mass other than 1, unequal
+# planet masses and planets at unequal distances from the star.  The expected
+# answers come from the definitions written out here with numpy, not from the
+# oracle: an encounter is two planets closer than
+# ((m_i + m_j) / (3 m0))^(1/3) (r_i + r_j) / 2 with r the distance to the star,
+# an ejection a planet farther than r_eject from the star.
+STAR_X = np.array([3.7, -2.1, 1.3])
+STAR_V = np.array([0.31, 0.17, -0.22])
+
+
+def _hill_radius(m0, mi, mj, ri, rj):
+    return ((mi + mj) / (3.0 * m0)) ** (1.0 / 3.0) * 0.5 * (ri + rj)
+
+
+def _pair_at_hill_fraction(m, frac, direction, ri=1.2):
+    """Star at STAR_X; planet 1 at distance ri from it along +x; planet 2 at
+    separation d from planet 1 along `direction`, with d = frac times the
+    mutual Hill radius of the resulting configuration (fixed-point solve of
+    d = frac R(d), a contraction since dR/dd < 1/2 here)."""
+    e = np.asarray(direction, float) / np.linalg.norm(direction)
+    x1 = STAR_X + np.array([ri, 0.0, 0.0])
+    d = 0.1
+    for _ in range(200):
+        rj = np.linalg.norm(x1 + d * e - STAR_X)
+        d = frac * _hill_radius(m[0], m[1], m[2], ri, rj)
+    x = np.array([STAR_X, x1, x1 + d * e])
+    rj = np.linalg.norm(x[2] - STAR_X)
+    assert abs(np.linalg.norm(x[2] - x[1]) / _hill_radius(m[0], m[1], m[2], ri, rj) - frac) < 1e-12
+    return x
+
+
+@pytest.mark.parametrize("direction", [(1.0, 0.0, 0.0), (0.6, 0.8, 0.0), (0.3, -0.4, 0.866)])
+def test_encounter_threshold_both_sides_displaced_star(ora, direction):
+    """0.99 of the mutual Hill radius is an encounter, 1.01 is not, for a star
+    of mass 1.7 off the origin and moving, planets of 3e-2 and 1e-2 at unequal
+    distances from it.  A radius without the factor 3 (1.44x larger), with m0
+    dropped, measured from the origin, or from one planet's distance alone
+    flips one of the two answers."""
+    m = np.array([1.7, 3e-2, 1e-2])
+    v = np.array([STAR_V, STAR_V + [0.0, 0.9, 0.1], STAR_V + [0.1, 0.85, 0.0]])
+    for frac, expect in ((0.99, ora.ENCOUNTER), (1.01, ora.ACTIVE)):
+        x = _pair_at_hill_fraction(m, frac, direction)
+        assert ora.check_stop(m, x, v, 1, 100.0) == expect, (frac, direction)
+        assert ora.check_stop(m, x, v, 3, 100.0) == expect, (frac, direction)
+        assert ora.check_stop(m, x, v, 2, 100.0) == ora.ACTIVE   # encounter rule off
+
+
+def test_encounter_uses_the_pair_and_star_masses(ora):
+    """Same geometry, masses swapped between the planets: the criterion
+    depends on m_i + m_j only.  Raising m0 by 2% shrinks the radius by 0.66%
+    and turns 0.995 of the radius into a separation outside it."""
+    m = np.array([1.7, 3e-2, 1e-2])
+    v = np.zeros((3, 3))
+    x = _pair_at_hill_fraction(m, 0.995, (0.6, 0.8, 0.0))
+    assert ora.check_stop(m, x, v, 1, 100.0) == ora.ENCOUNTER
+    assert ora.check_stop(m[[0, 2, 1]], x, v, 1, 100.0) == ora.ENCOUNTER
+    m2 = m.copy()
+    m2[0] *= 1.02
+    assert ora.check_stop(m2, x, v, 1, 100.0) == ora.ACTIVE
+
+
+def test_encounter_checks_every_planet_pair(ora):
+    """Four planets; only the pair (2, 4) is inside its Hill radius (0.98),
+    the star is displaced: the rule must visit pairs that do not involve
+    planet 1 and are not adjacent in index."""
+    m = np.array([0.8, 1e-3, 2e-2, 5e-3, 1e-2])
+    sub = _pair_at_hill_fraction(np.array([m[0], m[2], m[4]]), 0.98, (0.0, 1.0, 0.2), ri=1.6)
+    x = np.array([STAR_X, STAR_X + [0.0, -1.0, 0.0], sub[1], STAR_X + [-3.0, 0.5, 0.0], sub[2]])
+    v = np.zeros((5, 3))
+    assert ora.check_stop(m, x, v, 1, 100.0) == ora.ENCOUNTER
+    sub = _pair_at_hill_fraction(np.array([m[0], m[2], m[4]]), 1.02, (0.0, 1.0, 0.2), ri=1.6)
+    x[2], x[4] = sub[1], sub[2]
+    assert ora.check_stop(m, x, v, 1, 100.0) == ora.ACTIVE
+
+
+@pytest.mark.parametrize("offset", [(0.0, 1.0, 0.0), (-1.0, 0.0, 0.0), (0.48, -0.6, 0.64)])
+def test_ejection_threshold_both_sides_displaced_star(ora, offset):
+    """A planet at r_eject (1 +- 1e-9) from a star sitting 50 length units off
+    the origin: only the outer one is ejected.  Distances from the origin
+    (50 +- 100 along some lines, 112 across) give the other answer on at least
+    one side."""
+    e = np.asarray(offset, float) / np.linalg.norm(offset)
+    star = np.array([50.0, 0.0, 0.0])
+    m = np.array([1.3, 1e-4, 2e-4])
+    v = np.array([STAR_V, STAR_V, STAR_V])
+    for r_eject in (100.0, 37.5):
+        for f, expect in ((1 + 1e-9, ora.EJECTED), (1 - 1e-9, ora.ACTIVE)):
+            x = np.array([star, star + [0.0, 0.0, 2.0], star + f * r_eject * e])
+            assert ora.check_stop(m, x, v, 2, r_eject) == expect, (r_eject, f, offset)
+            assert ora.check_stop(m, x, v, 1, r_eject) == ora.ACTIVE   # ejection rule off
+
+
+def test_ejection_from_origin_is_not_ejection(ora):
+    """Everything 150 units from the origin, all planets within 10 of the
+    star: nothing is ejected at r_eject = 100."""
+    m = np.array([1.0, 1e-4, 1e-4])
+    x = np.array([[150.0, 0, 0], [151.0, 0, 0], [140.0, 0, 0]])
+    assert ora.check_stop(m, x, np.zeros((3, 3)), 3, 100.0) == ora.ACTIVE
+
+
+def test_stop_rules_translation_invariant(ora):
+    """The rules depend on separations only: translating a whole
+    configuration never changes the verdict.  Configurations are drawn near
+    both thresholds (Hill fractions 0.95..1.05, distances r_eject x
+    0.99..1.01) so a criterion measured from the origin would change some."""
+    rng = np.random.default_rng(77)
+    m = np.array([1.7, 3e-2, 1e-2])
+    verdicts = set()
+    for k in range(40):
+        d = rng.normal(size=3)
+        x = _pair_at_hill_fraction(m, rng.uniform(0.95, 1.05), d)
+        if k % 2:
+            x[2] = x[0] + rng.uniform(0.99, 1.01) * 20.0 * d / np.linalg.norm(d)
+        for T in (np.zeros(3), rng.normal(scale=30.0, size=3)):
+            verdicts.add((k, ora.check_stop(m, x + T, np.zeros((3, 3)), 3, 20.0)))
+    by_k = {}
+    for k, s in verdicts:
+        by_k.setdefault(k, set()).add(s)
+    assert all(len(s) == 1 for s in by_k.values())
+    assert {next(iter(s)) for s in by_k.values()} >= {ora.ACTIVE, ora.ENCOUNTER, ora.EJECTED}
+
+
+def test_stop_rule_precedence(ora):
+    """Non-finite state outranks an encounter, which outranks an ejection."""
+    m = np.array([1.0, 3e-2, 1e-2, 1e-3])
+    x = _pair_at_hill_fraction(m[:3], 0.9, (0.0, 1.0, 0.0))
+    x = np.vstack([x, x[0] + [0.0, 0.0, 150.0]])
+    v = np.zeros((4, 3))
+    assert ora.check_stop(m, x, v, 3, 100.0) == ora.ENCOUNTER
+    assert ora.check_stop(m, x, v, 2, 100.0) == ora.EJECTED
+    v[3, 1] = np.inf
+    assert ora.check_stop(m, x, v, 3, 100.0) == ora.NONFINITE
+
+
+def _two_body_dt(x, v, eta):
+    """The pairwise step rule's closed form for two bodies,
+    eta r / sqrt(u_t^2 + 4 u_r^2)."""
+    r = x[1] - x[0]
+    u = v[1] - v[0]
+    rn = np.linalg.norm(r)
+    ur = (r @ u) / rn
+    return eta * rn / math.sqrt(u @ u - ur * ur + 4 * ur * ur)
+
+
+def test_stalled_dt_threshold_both_sides(ora):
+    """A proposed step below 1e-12 |t_end| stalls the system before it moves;
+    just above the threshold it steps (stopped here by max_steps).  Circular
+    two-body orbit, so the proposal is the closed form eta a / v and stays
+    within roundoff of it."""
+    m0, m1 = 1.0, 1e-3
+    x, v = kepler.two_body_state(m0, m1, 1.0, 0.0, 0.4)
+    m = np.array([m0, m1])
+    dt0 = _two_body_dt(x, v, 0.01)
+    stall = ora.integrate_adaptive(m, x, v, t_end=dt0 / 1e-12 * (1 + 1e-6), eta=0.01, stop_rules=0)
+    assert stall["status"] == ora.STALLED_DT and stall["steps"] == 0
+    assert np.array_equal(stall["pos"], x) and np.array_equal(stall["vel"], v) and stall["t"] == 0.0
+    assert abs(stall["dt_next"] - dt0) < 1e-12 * dt0
+    go = ora.integrate_adaptive(m, x, v, t_end=dt0 / 1e-12 * (1 - 1e-6), eta=0.01, stop_rules=0,
+                                max_steps=3)
+    assert go["status"] == ora.MAXSTEPS and go["steps"] == 3
+    assert abs(go["t"] - 3 * dt0) < 1e-9 * dt0
+
+
+def test_stalled_dt_on_a_plunging_orbit(ora):
+    """A planet on a nearly radial orbit (pericentre 2e-6) falls toward the
+    star; the pairwise proposal shrinks with the separation.  The system
+    stalls at the first step whose proposal is below 1e-12 t_end, and every
+    earlier proposal was at or above it.  Each proposal is the closed form at
+    the step's last evaluation point, which the committed state matches to
+    the corrector's last change (checked at 1e-6)."""
+    m0, m1 = 1.0, 1e-6
+    x, v = kepler.two_body_state(m0, m1, 1.0, 1 - 2e-6, math.pi * 1.5)
+    assert (x[1] - x[0]) @ (v[1] - v[0]) < 0   # falling in
+    m = np.array([m0, m1])
+    t_end = 1e4
+    out = ora.integrate_adaptive(m, x, v, t_end=t_end, eta=0.01, stop_rules=0)
+    assert out["status"] == ora.STALLED_DT and out["steps"] > 10
+    assert abs(out["dt_next"] - _two_body_dt(out["pos"], out["vel"], 0.01)) < 1e-6 * out["dt_next"]
+    assert out["dt_next"] < 1e-12 * t_end
+    prev = ora.integrate_adaptive(m, x, v, t_end=t_end, eta=0.01, stop_rules=0,
+                                  max_steps=out["steps"] - 1)
+    assert prev["status"] == ora.MAXSTEPS
+    assert prev["dt_next"] >= 1e-12 * t_end
+    assert abs(prev["dt_next"] - _two_body_dt(prev["pos"], prev["vel"], 0.01)) < 1e-6 * prev["dt_next"]
+
+
+def test_max_steps_stops_after_exactly_that_many(ora):
+    m, x, v = _three_body_system(2)
+    for k in (1, 7, 40):
+        out = ora.integrate_adaptive(m, x, v, t_end=1e3, eta=0.01, max_steps=k)
+        assert out["status"] == ora.MAXSTEPS and out["steps"] == k
+        more = ora.integrate_adaptive(m, out["pos"], out["vel"], t_end=1e3, eta=0.01, max_steps=k + 5,
+                                      t0=out["t"], acc=out["acc"], jerk=out["jerk"],
+                                      dt_next=out["dt_next"], steps=out["steps"])
+        ref = ora.integrate_adaptive(m, x, v, t_end=1e3, eta=0.01, max_steps=k + 5)
+        assert more["steps"] == k + 5 and np.array_equal(more["pos"], ref["pos"])
+
+
 def test_adaptive_hyperbolic_planet_is_ejected(ora):
     m = np.array([1.0, 1e-5, 1e-5])
     x = np.array([[0.0, 0, 0], [1.0, 0, 0], [0, 3.0, 0]])
