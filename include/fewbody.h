@@ -157,10 +157,31 @@ fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body,
                                     void *d_workspace, size_t ws_bytes,
                                     void *hip_stream, fb_ensemble **out);
 
+/* Resume from a checkpoint (the state Section 4.4 copies between host and
+ * device, with what Algorithm 2 carries from one step to the next): an
+ * ensemble like fb_ensemble_create's from HOST arrays, whose (a0, j0) are
+ * the given acc0/jerk0 [N][3] instead of a set-up evaluation, with each
+ * system's time t [n_sys] (NULL: 0), carried adaptive step dt_next [n_sys]
+ * (finite, >= 0; NULL: none carried), status [n_sys] (FB_SYS_ACTIVE ..
+ * FB_SYS_MAXSTEPS; NULL: FB_SYS_DONE) and steps since creation [n_sys]
+ * (>= 0; NULL: 0).  With the values fb_get_state and fb_get_hermite_state
+ * returned, later integration continues bitwise as the checkpointed
+ * ensemble would have.  Validation and ownership as fb_ensemble_create;
+ * FB_E_INVAL names the first bad value. */
+fb_status fb_ensemble_restore(int32_t n_sys, const int32_t *n_body,
+                              const double *mass, const double *pos,
+                              const double *vel, const double *acc0,
+                              const double *jerk0, const double *t,
+                              const double *dt_next, const int32_t *status,
+                              const int64_t *steps, void *hip_stream,
+                              fb_ensemble **out);
+
 /* Advance every active system by exactly n_steps fixed steps of size dt
- * (dt may be negative: backward integration).  Times become
- * t_start + n_steps * dt.  o: schedule/quantum/stop options (o->adaptive
- * must be 0); NULL = defaults. */
+ * (Algorithm 1's loop with a step count in place of a destination time;
+ * each step is Algorithm 2's P(EC)^2).  dt may be negative: backward
+ * integration.  Times become t_start + n_steps * dt.  o: schedule/quantum/
+ * stop options (o->adaptive must be 0); NULL = defaults.  Asynchronous on
+ * the ensemble's stream; FB_E_INVAL for a bad argument. */
 fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt,
                              const fb_opts *o);
 
@@ -267,18 +288,23 @@ fb_status fb_integrate_rkck(fb_ensemble *e, double t_end, double dt, double eps,
 fb_status fb_integrate(fb_ensemble *e, double t_end, double dt,
                        const fb_opts *o);
 
-/* Wait for all work enqueued on the ensemble's stream. */
+/* Wait for all work enqueued on the ensemble's stream (the host's wait for
+ * the device before it examines results, Section 5.3). */
 fb_status fb_synchronize(fb_ensemble *e);
 
-/* Copy state to HOST arrays in the caller's system order; any pointer may be
- * NULL to skip it.  pos, vel [N][3]; t [n_sys]; status [n_sys] (FB_SYS_*);
- * steps [n_sys] = steps taken since creation. */
+/* Copy state to HOST arrays in the caller's system order (the device-to-host
+ * ensemble copy of Section 4.4); any pointer may be NULL to skip it.
+ * pos, vel [N][3]; t [n_sys]; status [n_sys] (FB_SYS_*); steps [n_sys] =
+ * steps taken since creation.  Synchronises the ensemble's stream. */
 fb_status fb_get_state(fb_ensemble *e, double *pos, double *vel, double *t,
                        int32_t *status, int64_t *steps);
 
-/* Checkpoint part of the state: the carried (a0, j0) of every body, [N][3]
- * each, and each system's carried adaptive step (dt_next, [n_sys]); any
- * pointer may be NULL. */
+/* Checkpoint part of the state (what Algorithm 2 carries into the next
+ * step, copied to the host as Section 4.4's ensemble copies are): the
+ * carried (a0, j0) of every body, [N][3] each, and each system's carried
+ * adaptive step (dt_next, [n_sys]); any pointer may be NULL.  With
+ * fb_get_state's outputs it is what fb_ensemble_restore takes.
+ * FB_E_STATE while the ensemble holds MVS state.  Synchronises. */
 fb_status fb_get_hermite_state(fb_ensemble *e, double *acc0, double *jerk0,
                                double *dt_next);
 
@@ -291,8 +317,35 @@ fb_status fb_diagnostics(fb_ensemble *e, double *energy, double *angmom);
 /* Number of systems and total bodies. */
 fb_status fb_ensemble_shape(const fb_ensemble *e, int32_t *n_sys, int64_t *n_bodies);
 
+/* Wait for the ensemble's stream, then free its device state (the library's
+ * own allocation; a caller workspace is left to the caller) and the handle.
+ * NULL is a no-op. */
 fb_status fb_ensemble_destroy(fb_ensemble *e);
 
+/* ------------------------------------------------ stateless batch steps */
+/* Bytes of device workspace fb_hermite_steps_device needs for n_sys systems
+ * of n bodies; 0 on invalid input. */
+size_t fb_hermite_steps_workspace_bytes(int32_t n_sys, int32_t n);
+
+/* n_steps fixed Hermite steps of dt (Eq. 3 predictor, Eq. 4 corrector twice
+ * per step, Algorithm 2; the set-up evaluation of Algorithm 1's "prepare"
+ * first) of n_sys systems of n bodies (2..FB_MAX_SMALL_BODIES) held in the
+ * caller's DEVICE arrays, in place: d_mass [N], d_pos and d_vel [N][3]
+ * body-major, N = n_sys * n; d_status [n_sys] (may be NULL) gets each
+ * system's FB_SYS_* code (FB_SYS_DONE, or FB_SYS_NONFINITE for a system
+ * whose state became non-finite).  The packed state lives in the caller's
+ * workspace of ws_bytes >= fb_hermite_steps_workspace_bytes(n_sys, n)
+ * bytes, 256-byte aligned, which the call only borrows.  Pure stream work:
+ * no host synchronisation, no allocation, no read-back, so the inputs are
+ * not checked on the host (a non-finite value ends its system as
+ * FB_SYS_NONFINITE).  Same kernels and plan as an ensemble's plain
+ * schedule: the results equal fb_ensemble_create_device + fb_integrate_steps
+ * + fb_get_state bitwise.  FB_E_INVAL for bad sizes or pointers, FB_E_NOMEM
+ * for a short workspace. */
+fb_status fb_hermite_steps_device(int32_t n_sys, int32_t n, const double *d_mass,
+                                  double *d_pos, double *d_vel, int32_t *d_status,
+                                  int64_t n_steps, double dt, void *d_workspace,
+                                  size_t ws_bytes, void *hip_stream);
 /* ---------------------------------------------------------------- plans */
 /* The launch plan of body count n: lane mapping (FB_MAP_*) and waves per
  * workgroup (1..4) of its plain launches.  System-per-lane is built for
@@ -350,6 +403,13 @@ fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
  * current device and synchronises.  (A measurement utility; it computes
  * nothing of the method.) */
 fb_status fb_fp64_fma_ceiling(double *tflops);
+
+/* The reciprocal square root every pair evaluation uses (Eq. 1's 1/|r|^3
+ * and the jerk's 1/|r|^2 come from it; Section 4.4 discusses the hardware
+ * rsqrt the paper relied on), applied elementwise to n DEVICE values x > 0:
+ * d_out[i] = 1/sqrt(d_in[i]).  Asynchronous on the stream.  A measurement
+ * utility for its accuracy; it computes nothing else. */
+fb_status fb_eval_rsqrt(const double *d_in, double *d_out, int64_t n, void *hip_stream);
 
 /* ---------------------------------------------------------------- serving */
 /* A continuous-batching integration server.  Requests (an ensemble with its

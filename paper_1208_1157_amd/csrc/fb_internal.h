@@ -139,6 +139,16 @@ int large_bodies_per_lane(int n);
 // FP64 FMA issue-ceiling probe: blocks x 256 lanes, iters x kFmaChains FMAs
 // per lane (kFmaChains = 16); out holds blocks x 256 doubles.
 hipError_t launch_fma_probe(double *out, int blocks, int iters, hipStream_t s);
+// The pair evaluation's reciprocal square root, elementwise (accuracy check).
+hipError_t launch_rsqrt(const double *in, double *out, long long n, hipStream_t s);
+// Checkpoint restore of the carried (a0, j0), adaptive step, step count and
+// status of every system of B from caller-order arrays.
+hipError_t launch_restore(const Bucket &B, const long long *orig_off, const double *acc,
+                          const double *jerk, const double *dtn, const long long *steps,
+                          const int *status, hipStream_t s);
+// Identity slot map and body offsets (o * n) of a single homogeneous bucket
+// holding the caller's systems in order; clears *bad.
+hipError_t launch_identity_tables(const Bucket &B, long long *orig_off, int *bad, hipStream_t s);
 size_t persistent_lds_bytes(int spl_class, int waves_per_group);
 int persistent_max_groups_per_cu(int adv, int spl_class, int waves_per_group);
 // Largest n a persistent tile runs system-per-lane for, by kernel class.

@@ -3159,6 +3159,56 @@ __global__ __launch_bounds__(256) void k_fma_probe(double *out, int iters, doubl
 
 inline dim3 grid_for(int n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
 
+// The device reciprocal square root of every pair evaluation, elementwise
+// over n values (a check of its accuracy against a correctly rounded
+// reference).
+__global__ void k_rsqrt(const double *__restrict__ in, double *__restrict__ out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = rsqrt_nr(in[i]);
+}
+
+// Checkpoint restore: the carried (a0, j0) rows and each system's clock
+// (adaptive step, steps since creation, status) from caller-order arrays.
+// Positions, velocities, masses and t were packed already.
+__global__ void k_restore(Bucket B, const long long *__restrict__ orig_off,
+                          const double *__restrict__ acc, const double *__restrict__ jerk,
+                          const double *__restrict__ dtn, const long long *__restrict__ steps,
+                          const int *__restrict__ status)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B.count)
+        return;
+    const size_t pitch = B.pitch;
+    const int n = B.n;
+    const int o = B.orig[s];
+    const long long base = orig_off[o];
+    for (int b = 0; b < n; ++b)
+        for (int c = 0; c < 3; ++c) {
+            const size_t row = 3 * (base + b) + c;
+            B.st[((R_A + c) * n + b) * pitch + s] = acc[row];
+            B.st[((R_J + c) * n + b) * pitch + s] = jerk[row];
+        }
+    B.dtn[s] = dtn[o];
+    B.steps[s] = steps[o];
+    B.status[s] = status[o];
+}
+
+// Tables of a single homogeneous bucket whose slots are the caller's
+// systems in order: slot -> system (padding slots -> 0), body offsets
+// o * n, and the input-check flag cleared.
+__global__ void k_identity_tables(Bucket B, long long *__restrict__ orig_off, int *bad)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < B.pitch)
+        B.orig[s] = s < B.count ? s : 0;
+    if (s <= B.count)
+        orig_off[s] = (long long)s * B.n;
+    if (s == 0)
+        *bad = 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -3618,6 +3668,35 @@ hipError_t launch_plain_rkck(const Bucket &B, int waves_per_group, const StepPar
 hipError_t launch_fma_probe(double *out, int blocks, int iters, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fma_probe, dim3(blocks), dim3(256), 0, s, out, iters, 0.999999, 1e-6);
+    return hipGetLastError();
+}
+
+hipError_t launch_rsqrt(const double *in, double *out, long long n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const long long blocks = (n + 255) / 256;
+    if (blocks > INT_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rsqrt, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_restore(const Bucket &B, const long long *orig_off, const double *acc,
+                          const double *jerk, const double *dtn, const long long *steps,
+                          const int *status, hipStream_t s)
+{
+    if (B.count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_restore, grid_for(B.count, 256), dim3(256), 0, s, B, orig_off, acc, jerk,
+                       dtn, steps, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity_tables(const Bucket &B, long long *orig_off, int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_identity_tables, grid_for(B.pitch + 1, 256), dim3(256), 0, s, B,
+                       orig_off, bad);
     return hipGetLastError();
 }
 

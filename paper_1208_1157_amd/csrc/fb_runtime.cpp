@@ -32,7 +32,9 @@ using namespace fb::rt;
 // errors
 // ---------------------------------------------------------------------------
 namespace {
-thread_local std::string g_err;
+// Message of the calling thread's last failure (a fixed buffer, so that
+// reporting an error allocates nothing).
+thread_local char g_err[512];
 }  // namespace
 
 namespace fb {
@@ -40,12 +42,10 @@ namespace rt {
 
 fb_status fail(fb_status code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -875,6 +875,83 @@ fb_status fb_ensemble_create_device(int32_t n_sys, const int32_t *n_body, const 
     return FB_OK;
 }
 
+fb_status fb_ensemble_restore(int32_t n_sys, const int32_t *n_body, const double *mass,
+                              const double *pos, const double *vel, const double *acc0,
+                              const double *jerk0, const double *t, const double *dt_next,
+                              const int32_t *status, const int64_t *steps, void *hip_stream,
+                              fb_ensemble **out)
+{
+    if (!out)
+        return fail(FB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    if (!make_layout(n_sys, n_body, L))
+        return fail(FB_E_INVAL, "n_sys must be >= 0 and every n_body in 2..%d", kMaxLargeBodies);
+    const size_t N = (size_t)L.n_bodies, ns = (size_t)n_sys;
+    if (N && (!acc0 || !jerk0))
+        return fail(FB_E_INVAL, "acc0 and jerk0 are required");
+    if (N && (!finite_all(acc0, 3 * N) || !finite_all(jerk0, 3 * N)))
+        return fail(FB_E_INVAL, "acc0 and jerk0 must be finite");
+    for (size_t k = 0; k < ns; ++k) {
+        if (dt_next && !(std::isfinite(dt_next[k]) && dt_next[k] >= 0.0))
+            return fail(FB_E_INVAL, "dt_next[%zu] must be finite and >= 0", k);
+        if (status && (status[k] < FB_SYS_ACTIVE || status[k] > FB_SYS_MAXSTEPS))
+            return fail(FB_E_INVAL, "status[%zu] must be a Hermite status (0..%d)", k,
+                        FB_SYS_MAXSTEPS);
+        if (steps && steps[k] < 0)
+            return fail(FB_E_INVAL, "steps[%zu] must be >= 0", k);
+    }
+    fb_ensemble *e = nullptr;
+    fb_status st = fb_ensemble_create(n_sys, n_body, mass, pos, vel, t, hip_stream, &e);
+    if (st != FB_OK)
+        return st;
+    if (ns) {
+        // stage acc | jerk | dt_next | steps | status (fits the input staging)
+        std::vector<double> dtn(ns, 0.0);
+        std::vector<long long> stp(ns, 0);
+        std::vector<int> sts(ns, FB_SYS_DONE);
+        for (size_t k = 0; k < ns; ++k) {
+            if (dt_next)
+                dtn[k] = dt_next[k];
+            if (steps)
+                stp[k] = steps[k];
+            if (status)
+                sts[k] = status[k];
+        }
+        double *d_acc = e->d_staging, *d_jerk = d_acc + 3 * N, *d_dtn = d_jerk + 3 * N;
+        long long *d_steps = (long long *)(d_dtn + ns);
+        int *d_status = (int *)(d_steps + ns);
+        hipError_t err = hipMemcpyAsync(d_acc, acc0, 24 * N, hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(d_jerk, jerk0, 24 * N, hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(d_dtn, dtn.data(), 8 * ns, hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(d_steps, stp.data(), 8 * ns, hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(d_status, sts.data(), 4 * ns, hipMemcpyHostToDevice, e->stream);
+        for (size_t b = 0; err == hipSuccess && b < e->buckets.size(); ++b)
+            err = launch_restore(e->buckets[b], e->d_orig_off, d_acc, d_jerk, d_dtn, d_steps,
+                                 d_status, e->stream);
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(e->stream);   // the host vectors die at return
+        if (err != hipSuccess) {
+            free_ensemble(e);
+            return hip_fail(err, "checkpoint restore");
+        }
+    }
+    *out = e;
+    return FB_OK;
+}
+
+fb_status fb_eval_rsqrt(const double *d_in, double *d_out, int64_t n, void *hip_stream)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)))
+        return fail(FB_E_INVAL, "n must be >= 0 and d_in, d_out device pointers");
+    FB_HIP(launch_rsqrt(d_in, d_out, (long long)n, (hipStream_t)hip_stream));
+    return FB_OK;
+}
+
 fb_status fb_integrate_steps(fb_ensemble *e, int64_t n_steps, double dt, const fb_opts *po)
 {
     if (!e)
@@ -1485,7 +1562,7 @@ fb_status fb_profile_read(double *kernel_ms, int64_t *launches)
     return FB_OK;
 }
 
-const char *fb_last_error(void) { return g_err.c_str(); }
+const char *fb_last_error(void) { return g_err; }
 
 fb_status fb_fp64_fma_ceiling(double *tflops)
 {

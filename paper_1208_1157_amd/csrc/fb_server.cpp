@@ -25,6 +25,7 @@
 #include "fb_runtime_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <chrono>
 #include <climits>
@@ -215,7 +216,9 @@ struct Request {
     std::array<int, kMaxBodies + 1> cnt{};
     double t_end = 0.0, dt = 0.0;
     int state = FB_REQ_QUEUED;
-    bool cancel = false;
+    // set by fb_server_cancel (under the server lock), read by the worker
+    // between quanta without it
+    std::atomic<bool> cancel{false};
     AuxLayout aux;
     size_t aux_off = 0;
     bool has_aux = false;
@@ -418,6 +421,22 @@ bool reserve(fb_server *S, Request *R)
         }
     }
     return true;
+}
+
+// Free a request's host copies of its inputs (once its uploads completed),
+// and with `outputs` its host results too.
+void drop_payload(Request *R, bool outputs)
+{
+    std::vector<double>().swap(R->mass);
+    std::vector<double>().swap(R->pos);
+    std::vector<double>().swap(R->vel);
+    if (outputs) {
+        std::vector<double>().swap(R->out_pos);
+        std::vector<double>().swap(R->out_vel);
+        std::vector<double>().swap(R->out_t);
+        std::vector<int32_t>().swap(R->out_status);
+        std::vector<int64_t>().swap(R->out_steps);
+    }
 }
 
 void release_request(fb_server *S, Request *R)
@@ -765,6 +784,7 @@ void worker_main(fb_server *S)
             for (auto it = S->queue.begin(); it != S->queue.end();) {
                 if ((*it)->cancel) {
                     (*it)->state = FB_REQ_CANCELLED;
+                    drop_payload(*it, true);
                     it = S->queue.erase(it);
                     S->cv_done.notify_all();
                 } else {
@@ -805,13 +825,19 @@ void worker_main(fb_server *S)
             err = run_quantum(S, finished, sys_steps, spread);
             t1 = now_s();
         }
+        if (err == FB_OK)   // the quantum synchronised: the admitted uploads are done
+            for (Request *R : admitted)
+                drop_payload(R, false);
         std::lock_guard<std::mutex> lk(S->mu);
         if (err != FB_OK) {
             S->worker_status = err;
             S->worker_error = fb_last_error();
+            (void)hipStreamSynchronize(S->stream);
             for (auto &kv : S->all)
-                if (kv.second->state == FB_REQ_QUEUED || kv.second->state == FB_REQ_RUNNING)
+                if (kv.second->state == FB_REQ_QUEUED || kv.second->state == FB_REQ_RUNNING) {
                     kv.second->state = FB_REQ_FAILED;
+                    drop_payload(kv.second.get(), true);
+                }
             S->queue.clear();
             S->resident.clear();
             S->cv_done.notify_all();
@@ -827,7 +853,9 @@ void worker_main(fb_server *S)
         for (Request *R : finished) {
             R->t_done = td;
             R->state = R->cancel ? FB_REQ_CANCELLED : FB_REQ_DONE;
-            if (!R->cancel)
+            if (R->cancel)
+                drop_payload(R, true);
+            else
                 S->st.completed++;
             release_request(S, R);
             S->resident.erase(std::find(S->resident.begin(), S->resident.end(), R));

@@ -86,6 +86,11 @@ _SIGS = {
     "fb_ensemble_create": (ctypes.c_int, [_i32, _p, _p, _p, _p, _p, _p, ctypes.POINTER(_p)]),
     "fb_ensemble_create_device": (ctypes.c_int, [_i32, _p, _p, _p, _p, _p, _p, _sz, _p,
                                                  ctypes.POINTER(_p)]),
+    "fb_ensemble_restore": (ctypes.c_int, [_i32, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                                           ctypes.POINTER(_p)]),
+    "fb_hermite_steps_workspace_bytes": (_sz, [_i32, _i32]),
+    "fb_hermite_steps_device": (ctypes.c_int, [_i32, _i32, _p, _p, _p, _p, _i64, _d, _p, _sz, _p]),
+    "fb_eval_rsqrt": (ctypes.c_int, [_p, _p, _i64, _p]),
     "fb_integrate_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate_mvs": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_log_bytes": (_sz, [_i32, _p, _i32, _i32]),
@@ -200,6 +205,48 @@ def profile_read():
     return ms.value, n.value
 
 
+def eval_rsqrt(x):
+    """The library's device reciprocal square root applied to a float64 CUDA
+    tensor (fb_eval_rsqrt); returns a new tensor."""
+    import torch
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    _check(_lib.fb_eval_rsqrt(_ptr(x), _ptr(out), int(x.numel()),
+                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return out
+
+
+def hermite_steps_device(n, mass, pos, vel, n_steps, dt, status=None, workspace=None):
+    """n_steps fixed Hermite steps of the systems of n bodies held in float64
+    CUDA tensors mass [N], pos/vel [N, 3] (N = n_sys * n), in place, on
+    torch's current stream (fb_hermite_steps_device).  status: optional int32
+    CUDA tensor [n_sys] for the systems' FB_SYS_* codes.  workspace: optional
+    uint8 CUDA tensor (allocated here when None)."""
+    import torch
+    for t_ in (mass, pos, vel):
+        if not (isinstance(t_, torch.Tensor) and t_.is_cuda and t_.dtype == torch.float64
+                and t_.is_contiguous()):
+            raise FewbodyError(E_INVAL, "mass, pos and vel must be contiguous float64 CUDA tensors")
+    N = int(mass.numel())
+    if n < 2 or N % n or pos.numel() != 3 * N or vel.numel() != 3 * N:
+        raise FewbodyError(E_INVAL, "pos/vel must hold 3 values per body and N a multiple of n")
+    n_sys = N // n
+    if status is not None and not (status.is_cuda and status.dtype == torch.int32
+                                   and status.numel() == n_sys):
+        raise FewbodyError(E_INVAL, "status must be an int32 CUDA tensor of n_sys entries")
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ws = int(_lib.fb_hermite_steps_workspace_bytes(n_sys, int(n)))
+    if ws == 0 and n_sys > 0:
+        raise FewbodyError(E_INVAL, "invalid batch shape")
+    if workspace is None:
+        workspace = torch.empty(ws + 256, dtype=torch.uint8, device=mass.device)
+    addr = (workspace.data_ptr() + 255) // 256 * 256
+    avail = workspace.numel() - (addr - workspace.data_ptr())
+    _check(_lib.fb_hermite_steps_device(n_sys, int(n), _ptr(mass), _ptr(pos), _ptr(vel), _ptr(status),
+                                        int(n_steps), float(dt), ctypes.c_void_p(addr),
+                                        ctypes.c_size_t(max(avail, 0)), sp))
+
+
 def workspace_bytes(n_body) -> int:
     nb = np.ascontiguousarray(n_body, dtype=np.int32)
     return int(_lib.fb_workspace_bytes(int(nb.shape[0]), _ptr(nb)))
@@ -215,7 +262,7 @@ class Ensemble:
     allocates the device state itself.
     """
 
-    def __init__(self, n_body, mass, pos, vel, t0=None, stream=None, host=False):
+    def __init__(self, n_body, mass, pos, vel, t0=None, stream=None, host=False, checkpoint=None):
         import torch
         self._torch = torch
         self.n_body = np.ascontiguousarray(n_body, dtype=np.int32)
@@ -224,6 +271,26 @@ class Ensemble:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._handle = ctypes.c_void_p()
         sp = ctypes.c_void_p(self.stream.cuda_stream)
+        if checkpoint is not None:
+            # fb_ensemble_restore: checkpoint holds acc, jerk, t, dt_next, status, steps
+            m = np.ascontiguousarray(mass, dtype=np.float64)
+            x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+            v = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+            c = {k: checkpoint.get(k) for k in ("acc", "jerk", "t", "dt_next", "status", "steps")}
+            arr = {
+                "acc": np.ascontiguousarray(c["acc"], dtype=np.float64).reshape(-1, 3),
+                "jerk": np.ascontiguousarray(c["jerk"], dtype=np.float64).reshape(-1, 3),
+                "t": None if c["t"] is None else np.ascontiguousarray(c["t"], dtype=np.float64),
+                "dt_next": None if c["dt_next"] is None else np.ascontiguousarray(c["dt_next"], dtype=np.float64),
+                "status": None if c["status"] is None else np.ascontiguousarray(c["status"], dtype=np.int32),
+                "steps": None if c["steps"] is None else np.ascontiguousarray(c["steps"], dtype=np.int64),
+            }
+            self._keep = None
+            _check(_lib.fb_ensemble_restore(self.n_sys, _ptr(self.n_body), _ptr(m), _ptr(x), _ptr(v),
+                                            _ptr(arr["acc"]), _ptr(arr["jerk"]), _ptr(arr["t"]),
+                                            _ptr(arr["dt_next"]), _ptr(arr["status"]), _ptr(arr["steps"]),
+                                            sp, ctypes.byref(self._handle)))
+            return
         if host:
             m = np.ascontiguousarray(mass, dtype=np.float64)
             x = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
@@ -390,6 +457,15 @@ class Ensemble:
         acc, jerk, dtn = np.empty((N, 3)), np.empty((N, 3)), np.empty(S)
         _check(_lib.fb_get_hermite_state(self._handle, _ptr(acc), _ptr(jerk), _ptr(dtn)))
         return acc, jerk, dtn
+
+    def checkpoint(self):
+        """Everything fb_ensemble_restore needs to continue this ensemble
+        bitwise: masses are the caller's; returns dict(pos, vel, acc, jerk,
+        t, dt_next, status, steps)."""
+        st = self.state()
+        acc, jerk, dtn = self.hermite_state()
+        return {"pos": st["pos"], "vel": st["vel"], "acc": acc, "jerk": jerk, "t": st["t"],
+                "dt_next": dtn, "status": st["status"], "steps": st["steps"]}
 
     def diagnostics(self):
         E = np.empty(self.n_sys)

@@ -39,3 +39,142 @@ def assert_parity(n_body, gpu_pos, gpu_vel, ora_pos, ora_vel, tol=REL_TOL, label
         f"{label}: parity failed: max rel err x={ex.max():.3e} v={ev.max():.3e} "
         f"(system {worst}, n={n_body[worst]})")
     return ex.max(), ev.max()
+
+
+# ---------------------------------------------------------------------------
+# Adaptive runs: a system whose discrete decisions differ between the GPU and
+# the oracle is compared up to its first differing decision, and that decision
+# must sit within roundoff-scale reach of its threshold.
+# ---------------------------------------------------------------------------
+DECISION_MARGIN = 1e-8
+
+
+def stop_margins(mass, pos, r_eject):
+    """Relative distance of the oracle's state to each stop threshold: the
+    smallest |sep / R_hill - 1| over planet pairs, R_hill the mutual Hill
+    radius ((m_i + m_j) / (3 m0))^(1/3) (r_i + r_j) / 2 with r the distance
+    from the star, and the smallest |r / r_eject - 1| over planets."""
+    m = np.asarray(mass, dtype=np.float64)
+    x = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    r = np.linalg.norm(x[1:] - x[0], axis=1)
+    hill = np.inf
+    for i in range(1, len(m)):
+        for j in range(i + 1, len(m)):
+            sep = np.linalg.norm(x[i] - x[j])
+            rh = np.cbrt((m[i] + m[j]) / (3.0 * m[0])) * 0.5 * (r[i - 1] + r[j - 1])
+            hill = min(hill, abs(sep / rh - 1.0))
+    eject = float(np.min(np.abs(r / r_eject - 1.0))) if len(r) else np.inf
+    return hill, eject
+
+
+def explain_adaptive_mismatch(ora, system, t_end, eta, stop_rules, r_eject, paper_rule,
+                              rerun, got_status, got_steps, ref, margin=DECISION_MARGIN,
+                              tol=REL_TOL, max_steps=10**9):
+    """For one system whose final status or step count differs from the
+    oracle's `ref`: rerun both sides up to the step before the first differing
+    decision (rerun(k) returns the candidate's dict(pos, vel, t, status, steps)
+    after at most k steps), require parity there, then require the criterion
+    that flipped to lie within `margin` (relative) of its threshold in the
+    oracle's state.  Returns (k1, criterion, its margin); raises
+    AssertionError with the numbers otherwise."""
+    m, x0, v0 = system
+    kw = dict(t_end=t_end, eta=eta, stop_rules=stop_rules, r_eject=r_eject, paper_rule=paper_rule)
+    k1 = min(int(got_steps), int(ref["steps"]))
+    assert k1 <= max_steps
+    events = []
+    for st, steps in ((int(got_status), int(got_steps)), (int(ref["status"]), int(ref["steps"]))):
+        events.append(st if steps == k1 else ora.ACTIVE)
+    assert events[0] != events[1], (k1, events)
+    crit = set()
+    for ev in events:
+        if ev == ora.ENCOUNTER:
+            crit.add("hill")
+        elif ev == ora.EJECTED:
+            crit.add("eject")
+        elif ev == ora.STALLED_DT:
+            crit.add("stall")
+        elif ev in (ora.NONFINITE, ora.MAXSTEPS):
+            raise AssertionError(f"decision {ev} at step {k1} cannot differ by roundoff")
+    if not crit:
+        crit.add("clamp")            # one side took its shortened last step at k1
+    pre = k1 - 1
+    if pre >= 1:
+        o_pre = ora.integrate_adaptive(m, x0, v0, max_steps=pre, **kw)
+        g_pre = rerun(pre)
+        assert o_pre["status"] == ora.MAXSTEPS and o_pre["steps"] == pre, o_pre["status"]
+        assert int(g_pre["status"]) == ora.MAXSTEPS and int(g_pre["steps"]) == pre, g_pre["status"]
+        n = [len(m)]
+        ex = per_system_rel_err(n, g_pre["pos"], o_pre["pos"])[0]
+        ev = per_system_rel_err(n, g_pre["vel"], o_pre["vel"])[0]
+        et = abs(float(g_pre["t"]) - o_pre["t"]) / max(abs(o_pre["t"]), 1e-300)
+        assert ex <= tol and ev <= tol and et <= tol, (
+            f"before the first differing decision (step {k1}): rel err x={ex:.3e} v={ev:.3e} t={et:.3e}")
+    else:
+        o_pre = ora.integrate_adaptive(m, x0, v0, max_steps=0, **kw)
+    o_k1 = ora.integrate_adaptive(m, x0, v0, max_steps=k1, **kw)
+    hill, eject = stop_margins(m, o_k1["pos"], r_eject)
+    margins = {
+        "hill": hill,
+        "eject": eject,
+        "clamp": abs(o_pre["t"] + o_pre["dt_next"] - t_end) / abs(t_end),
+        "stall": abs(o_k1["dt_next"] / (1e-12 * abs(t_end)) - 1.0),
+    }
+    worst = max(crit, key=lambda c: margins[c])
+    assert margins[worst] <= margin, (
+        f"decision '{worst}' at step {k1} differs but sits {margins[worst]:.3e} from its threshold "
+        f"(events gpu/oracle {events}; margins {margins})")
+    return k1, worst, margins[worst]
+
+
+def gpu_adaptive_rerun(fb, system, t_end, **opts):
+    """rerun(k) for explain_adaptive_mismatch: the system alone on the GPU,
+    integrated to t_end with the given fb.Opts fields and max_steps = k."""
+    m, x, v = system
+
+    def rerun(k):
+        E = fb.Ensemble(np.array([len(m)], dtype=np.int32), m, x, v)
+        E.integrate(t_end, 0.0, fb.Opts(max_steps=int(k), **opts))
+        st = E.state()
+        E.close()
+        return {"pos": st["pos"], "vel": st["vel"], "t": float(st["t"][0]),
+                "status": int(st["status"][0]), "steps": int(st["steps"][0])}
+    return rerun
+
+
+def check_adaptive_systems(fb, ora, ens, idx, st, t_end, eta, stop_rules, r_eject, paper_rule,
+                           refs=None, tol=REL_TOL, max_steps=10**9):
+    """Every system s in idx: if its status and step count equal the oracle's,
+    parity to tol (and t == t_end when done); otherwise its first differing
+    decision is explained (explain_adaptive_mismatch).  Returns (agree,
+    flipped, worst error, list of flips) and raises with the counts."""
+    off = ens.offsets
+    agree, flips, worst = 0, [], 0.0
+    for s in idx:
+        s = int(s)
+        system = ens.system(s)
+        o = refs[s] if refs is not None else ora.integrate_adaptive(
+            *system, t_end=t_end, eta=eta, stop_rules=stop_rules, r_eject=r_eject, paper_rule=paper_rule,
+            max_steps=max_steps)
+        sl = slice(off[s], off[s + 1])
+        if o["status"] == st["status"][s] and o["steps"] == st["steps"][s]:
+            agree += 1
+            n = [len(system[0])]
+            ex = per_system_rel_err(n, st["pos"][sl], o["pos"])[0]
+            ev = per_system_rel_err(n, st["vel"][sl], o["vel"])[0]
+            worst = max(worst, ex, ev)
+            assert ex <= tol and ev <= tol, (
+                f"system {s}: rel err x={ex:.3e} v={ev:.3e} (agree so far {agree}, flips {len(flips)})")
+            if o["status"] == ora.DONE:
+                assert st["t"][s] == t_end, (s, st["t"][s])
+            continue
+        rerun = gpu_adaptive_rerun(fb, system, t_end, adaptive=2 if paper_rule else 1, eta=eta,
+                                   stop_rules=stop_rules, r_eject=r_eject)
+        try:
+            k1, crit, margin = explain_adaptive_mismatch(
+                ora, system, t_end, eta, stop_rules, r_eject, paper_rule, rerun,
+                st["status"][s], st["steps"][s], o, tol=tol, max_steps=max_steps)
+        except AssertionError as exc:
+            raise AssertionError(f"system {s} (gpu {st['status'][s]}/{st['steps'][s]}, oracle "
+                                 f"{o['status']}/{o['steps']}; agree {agree}, flips {len(flips)}): {exc}")
+        flips.append((s, k1, crit, margin))
+    return agree, len(flips), worst, flips

@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 from paper_1208_1157_amd import gen
-from tests.helpers import REL_TOL, assert_parity, oracle_fixed, per_system_rel_err, threads
+from tests.helpers import (REL_TOL, assert_parity, check_adaptive_systems, oracle_fixed,
+                           per_system_rel_err, threads)
 
 pytestmark = pytest.mark.gpu
 
@@ -116,8 +117,11 @@ def test_parity_full_size_lifetimes_sampled(plans, ora):
     """All 65536 uneven-lifetime systems in the benchmark's launch
     configuration (persistent schedule, in-kernel compaction, 2000-step
     quanta, adaptive steps, both stop rules) over 3 inner orbits; 256 sampled
-    systems recomputed by the oracle.  Systems whose discrete decisions agree
-    (status, step count) match to 1e-10."""
+    systems recomputed by the oracle.  Every sampled system is checked:
+    where the discrete decisions agree (status, step count) the states match
+    to 1e-10; where they differ, both sides match to 1e-10 up to the step
+    before the first differing decision, and the criterion that flipped lies
+    within 1e-8 of its threshold (a last-bit decision)."""
     fb = plans
     ens, p = gen.workload("lifetimes_65536x4-8")
     t_end = 2 * math.pi * 3
@@ -130,40 +134,46 @@ def test_parity_full_size_lifetimes_sampled(plans, ora):
     assert np.all(st["status"] != fb.ACTIVE)
     rng = np.random.default_rng(4)
     idx = np.sort(rng.choice(ens.n_sys, 256, replace=False))
-    off = ens.offsets
-    agree, stopped = 0, 0
-    for s in idx:
-        s = int(s)
-        o = ora.integrate_adaptive(*ens.system(s), t_end=t_end, eta=p["eta"], stop_rules=3,
-                                   r_eject=p["r_eject"])
-        if o["status"] != st["status"][s] or o["steps"] != st["steps"][s]:
-            continue
-        agree += 1
-        stopped += o["status"] != ora.DONE
-        sl = slice(off[s], off[s + 1])
-        assert_parity([ens.n_body[s]], st["pos"][sl], st["vel"][sl], o["pos"], o["vel"],
-                      label=f"lifetimes system {s}")
-    say("agree", agree, "of", len(idx), "stopped by a rule", stopped)
-    assert agree >= 0.97 * len(idx), agree
+    agree, nflip, worst, flips = check_adaptive_systems(fb, ora, ens, idx, st, t_end, p["eta"], 3,
+                                                        p["r_eject"], False)
+    stopped = int(np.sum(np.isin(st["status"][idx], [fb.ENCOUNTER, fb.EJECTED])))
+    say("agree", agree, "flipped at a threshold", nflip, flips, "of", len(idx),
+        "stopped by a rule", stopped, "worst rel err", worst)
+    assert agree + nflip == len(idx)
 
 
 @pytest.mark.parametrize("steps", [1000, 20000])
 def test_energy_drift_within_twice_oracle(fb, ora, steps):
     """Energy drift |dE/E| of the GPU run within 2x the oracle's, over the
-    ensemble (max and RMS over systems, floor 1e-14).  Per-system values at
-    short horizons are roundoff noise, so the bar applies to the ensemble."""
+    ensemble (max and RMS over systems, floor 1e-14), at the horizon's end
+    and as the maximum over 10 evenly spaced sample points.  Per-system
+    values at short horizons are roundoff noise, so the bar applies to the
+    ensemble.  The GPU run is chunked at the sample points (bitwise the same
+    as one run); the oracle integrates each sample's horizon from the start."""
     ens, p = gen.workload("parity_1024x3", n_sys=256)
     say("energy drift 256x3", steps)
-    st, _, _ = run_gpu(fb, ens, steps, p["dt"])
-    X, V, _, _ = oracle_fixed(ora, ens, p["dt"], steps)
     E0, _ = ora.ensemble_energy(ens.n_body, ens.mass, ens.pos, ens.vel)
-    Eg, _ = ora.ensemble_energy(ens.n_body, ens.mass, st["pos"], st["vel"])
-    Eo, _ = ora.ensemble_energy(ens.n_body, ens.mass, X, V)
-    dg = np.abs((Eg - E0) / E0)
-    do = np.abs((Eo - E0) / E0)
-    say("drift max gpu/oracle", dg.max(), do.max(), "rms", np.sqrt((dg ** 2).mean()), np.sqrt((do ** 2).mean()))
-    assert dg.max() <= max(2 * do.max(), 1e-14)
-    assert np.sqrt((dg ** 2).mean()) <= max(2 * np.sqrt((do ** 2).mean()), 1e-14)
+    E = fb.from_gen(ens)
+    chunk = steps // 10
+    gmax = omax = grms = orms = 0.0
+    for k in range(1, 11):
+        E.integrate_steps(chunk, p["dt"])
+        st = E.state()
+        X, V, _, _ = oracle_fixed(ora, ens, p["dt"], k * chunk)
+        Eg, _ = ora.ensemble_energy(ens.n_body, ens.mass, st["pos"], st["vel"])
+        Eo, _ = ora.ensemble_energy(ens.n_body, ens.mass, X, V)
+        dg = np.abs((Eg - E0) / E0)
+        do = np.abs((Eo - E0) / E0)
+        gmax, omax = max(gmax, dg.max()), max(omax, do.max())
+        grms, orms = max(grms, np.sqrt((dg ** 2).mean())), max(orms, np.sqrt((do ** 2).mean()))
+        if k == 10:
+            say("end drift max gpu/oracle", dg.max(), do.max())
+            assert dg.max() <= max(2 * do.max(), 1e-14)
+            assert np.sqrt((dg ** 2).mean()) <= max(2 * np.sqrt((do ** 2).mean()), 1e-14)
+    E.close()
+    say("max over 10 samples: drift max gpu/oracle", gmax, omax, "rms", grms, orms)
+    assert gmax <= max(2 * omax, 1e-14), (gmax, omax)
+    assert grms <= max(2 * orms, 1e-14), (grms, orms)
 
 
 def test_diagnostics_kernel_matches_oracle(fb, ora):
@@ -311,31 +321,28 @@ def _adaptive_case(plans, ora, mapping, n_sys, orbits):
 @pytest.mark.parametrize("mapping", ["spl", "bpl"])
 def test_adaptive_with_stop_rules_parity(plans, ora, mapping):
     """Adaptive step + both stop rules on the uneven-lifetimes distribution
-    (tight, eccentric, chaotic systems) over a 5-orbit horizon: systems whose
-    discrete decisions agree with the oracle (final status, step count) match
-    it to 1e-10 relative; decisions may flip only on last-bit differences."""
+    (tight, eccentric, chaotic systems) over a 5-orbit horizon.  Every system
+    is checked: where the discrete decisions agree with the oracle (final
+    status, step count) the states match to 1e-10 relative; where they
+    differ, the two sides match to 1e-10 up to the step before the first
+    differing decision and the flipped criterion lies within 1e-8 of its
+    threshold."""
     fb, ens, st, outs, t_end = _adaptive_case(plans, ora, mapping, 128, 5)
-    off = ens.offsets
-    agree, worst = 0, 0.0
-    for s, o in enumerate(outs):
-        if o["status"] != st["status"][s] or o["steps"] != st["steps"][s]:
-            continue
-        agree += 1
-        sl = slice(off[s], off[s + 1])
-        ex = per_system_rel_err([ens.n_body[s]], st["pos"][sl], o["pos"])[0]
-        ev = per_system_rel_err([ens.n_body[s]], st["vel"][sl], o["vel"])[0]
-        worst = max(worst, ex, ev)
-        if o["status"] == ora.DONE:
-            assert st["t"][s] == t_end
-    say("agree", agree, "of", ens.n_sys, "worst rel err", worst)
-    assert agree >= 0.97 * ens.n_sys, agree
-    assert worst <= REL_TOL, worst
+    p = gen.workload("lifetimes_65536x4-8", n_sys=1)[1]
+    agree, nflip, worst, flips = check_adaptive_systems(fb, ora, ens, range(ens.n_sys), st, t_end,
+                                                        p["eta"], 3, p["r_eject"], False,
+                                                        refs=dict(enumerate(outs)))
+    say("agree", agree, "flipped at a threshold", nflip, flips, "of", ens.n_sys, "worst rel err", worst)
+    assert agree + nflip == ens.n_sys
 
 
 def test_adaptive_decisions_agree_long_horizon(plans, ora):
-    """Over 30 orbits the same systems retire for the same reason; step counts
-    agree within 1% where the status agrees (chaos amplifies last-bit step
-    differences, so trajectories are not compared here)."""
+    """Over 30 orbits these tight systems are chaotic: last-bit differences
+    grow past 1e-10 (two CPU builds of the oracle, with and without FMA
+    contraction, already differ by up to 2e-8 there), so trajectories are
+    not compared; per-system parity is claimed on the 5-orbit horizon above.
+    This checks the outcomes in aggregate: the same systems retire for the
+    same reason, and step counts agree within 1% where the status agrees."""
     fb, ens, st, outs, _ = _adaptive_case(plans, ora, "bpl", 96, 30)
     same = sum(o["status"] == st["status"][s] for s, o in enumerate(outs))
     close = sum(o["status"] == st["status"][s] and abs(o["steps"] - st["steps"][s]) <= 0.01 * o["steps"]
