@@ -16,16 +16,19 @@ Printed as one JSON line, with
                 kernel's hardware counters are on record; HBM traffic;
   p50/p99       solve latency of the serving trace (Poisson arrivals at
                 200 req/s, 1..4096 systems of 3..10 bodies per request);
-  cpu_baseline  the CPU oracle timed on this host's cores on a bounded sample;
-  extras        the serving report (with the single-tile latency floor);
-                with --extras also: ragged 65536 x (3..15), autotuned plans,
-                plain per-bucket launches vs the fused persistent launch;
-                uneven lifetimes 65536 x (4..8) with adaptive steps and stop
-                rules on a bounded horizon, plain launches vs persistent
-                quanta with compaction; Section 5.1's initial conditions at
-                Table 3's size, beside the paper's times; the MVS and
-                Runge-Kutta Cash-Karp integrators on the headline ensemble,
-                the ragged workload and the Section 5.1 systems.
+  load_store    HBM GB/s of the integration kernel's load and store phases:
+                zero-step launches (state in, nothing integrated, state out);
+  cpu_baseline  the CPU oracle timed on this host's cores on a bounded sample
+                (all threads of the CPU share, and one thread);
+  extras        the serving report (with the single-tile latency floor); the
+                ragged 65536 x (3..15) batch with autotuned plans, plain
+                per-bucket launches vs the fused persistent launch; uneven
+                lifetimes 65536 x (4..8) with adaptive steps and stop rules on
+                a bounded horizon, plain launches vs persistent quanta with
+                compaction; with --extras also Section 5.1's initial
+                conditions at Table 3's size, beside the paper's times; the
+                MVS and Runge-Kutta Cash-Karp integrators on the headline
+                ensemble, the ragged workload and the Section 5.1 systems.
 """
 from __future__ import annotations
 
@@ -50,11 +53,13 @@ MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596
                     "b0cf1370d8600140": 92417213.2, "d75718a170f1a208": 92400808.0,
                     "2e972ba6903455f7": 92417165.5, "b18c3be0358ab8a1": 92417237.0,
                     "1ed17940f99ee27b": 92404903.3}
-# Hardware counters of the same kernel on this workload (profiles/), keyed the
-# same way: FP64 flop per system-step from SQ_INSTS_VALU_FLOPS_FP64 x 64
-# lanes; the fraction of SIMD cycles issuing VALU (SQ_ACTIVE_INST_VALU x 4 over
-# GRBM_GUI_ACTIVE per XCD x SIMDs); the shader clock those cycles imply.
-MEASURED_COUNTERS = {
+# Hardware counters of the same kernel on this workload from rocprofv3 runs
+# (profiles/), keyed the same way: FP64 flop per system-step from
+# SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; the fraction of SIMD cycles issuing
+# VALU (SQ_ACTIVE_INST_VALU x 4 over GRBM_GUI_ACTIVE per XCD x SIMDs); the
+# shader clock those cycles implied on the profiled box.  They are records of
+# those runs, reported as such, not measurements of this run.
+PROFILED_COUNTERS = {
     "1c9dff3d544099cf": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9671,
                          "shader_clock_ghz": 2.018, "valu_insts_per_system_step": 388.01},
     "234f298587126ea3": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9753,
@@ -71,6 +76,11 @@ MEASURED_COUNTERS = {
                          "shader_clock_ghz": 1.939, "valu_insts_per_system_step": 388.01},
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
+HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
+PROFILE_SUMMARY = "profiles/k_plain_spl3_homog_131072x3.md"
+# The oracle's threads: every CPU of the affinity set, up to the host share of
+# one GPU on the GPU machines (16 threads).
+HOST_THREAD_SHARE = 16
 # Section 5.3, Table 3: seconds to integrate 131072 systems of the Section 5.1
 # initial conditions for one time unit with the Hermite integrator, on the
 # paper's four machines (context only: other hardware).
@@ -96,31 +106,91 @@ def flops_per_system_step(n: int) -> float:
     return 116.0 * n * (n - 1) / 2 + 120.0 * n
 
 
-def host_threads() -> int:
+def affinity_cpus() -> int:
     try:
-        c = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
     except AttributeError:
-        c = os.cpu_count() or 1
-    return max(1, min(16, c))
+        return os.cpu_count() or 1
 
 
-def cpu_baseline(ens, h, target_s=20.0):
-    """The oracle (plain FP64 C, one system per thread) on this host's cores,
-    on all systems of the ensemble for a bounded number of steps."""
+def host_threads() -> int:
+    return max(1, min(HOST_THREAD_SHARE, affinity_cpus()))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(ens, h, target_s=15.0, single_s=5.0):
+    """The oracle (plain FP64 C, one system per thread) on this host: all
+    systems of the ensemble on every thread of the CPU share for a bounded
+    number of steps, and a 2048-system subset on one thread."""
     import oracle
     nt = host_threads()
-    cal = ens.subset(range(min(ens.n_sys, 16384)))
-    t0 = time.perf_counter()
-    oracle.ensemble_fixed(cal.n_body, cal.mass, cal.pos, cal.vel, h, 40, nthreads=nt)
-    rate = cal.n_sys * 40 / (time.perf_counter() - t0)
-    steps = max(10, int(rate * target_s / ens.n_sys))
-    t0 = time.perf_counter()
-    oracle.ensemble_fixed(ens.n_body, ens.mass, ens.pos, ens.vel, h, steps, nthreads=nt)
-    dt = time.perf_counter() - t0
-    return {"value": ens.n_sys * steps / dt, "unit": "system-steps/s", "cores": nt,
-            "kind": "oracle",
-            "sample": f"all {ens.n_sys} systems x {steps} steps (of the workload's steps), "
-                      f"{dt:.1f} s, pthreads with a static partition by system"}
+
+    def rate_of(e, threads, seconds):
+        cal = e.subset(range(min(e.n_sys, 4096 * threads)))
+        t0 = time.perf_counter()
+        oracle.ensemble_fixed(cal.n_body, cal.mass, cal.pos, cal.vel, h, 20, nthreads=threads)
+        r = cal.n_sys * 20 / (time.perf_counter() - t0)
+        steps = max(10, int(r * seconds / e.n_sys))
+        t0 = time.perf_counter()
+        oracle.ensemble_fixed(e.n_body, e.mass, e.pos, e.vel, h, steps, nthreads=threads)
+        dt = time.perf_counter() - t0
+        return e.n_sys * steps / dt, steps, dt
+
+    all_rate, all_steps, all_dt = rate_of(ens, nt, target_s)
+    one = ens.subset(range(min(ens.n_sys, 2048)))
+    one_rate, one_steps, one_dt = rate_of(one, 1, single_s)
+    return {"value": all_rate, "unit": "system-steps/s", "cores": nt, "kind": "oracle",
+            "sample": f"all {ens.n_sys} systems x {all_steps} steps (of the workload's 100000) on {nt} "
+                      f"threads, {all_dt:.1f} s, pthreads with a static partition by system; single "
+                      f"thread: {one.n_sys} systems x {one_steps} steps, {one_dt:.1f} s",
+            "single_core_value": one_rate, "all_core_value": all_rate,
+            "threads_used": nt, "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity_cpus(),
+            "thread_cap": HOST_THREAD_SHARE, "cpu_model": cpu_model()}
+
+
+def load_store_probe(fb, ens, h, reps=10, scales=(1, 16)):
+    """HBM rate of the integration kernel's load and store phases: launches
+    of the headline kernel that load every system's state, take zero steps
+    (the step cap is already reached) and store it back, timed by the
+    library's kernel timer.  Algorithmic bytes per system: in 104 per body
+    (m, x, v, a0, j0) + 68 of clock, out 96 per body + 36 of clock.  The
+    headline ensemble, and the same systems tiled 16 times to amortise the
+    launch latency."""
+    import numpy as np
+    out = {}
+    for k in scales:
+        nb = np.tile(ens.n_body, k)
+        E = fb.Ensemble(nb, np.tile(ens.mass, k), np.tile(ens.pos, (k, 1)), np.tile(ens.vel, (k, 1)))
+        E.integrate_steps(1, h)
+        E.integrate_steps(1, h, fb.Opts(max_steps=1))     # warm: zero steps
+        fb.profile_read()
+        fb.profile_enable(True)
+        for _ in range(reps):
+            E.integrate_steps(1, h, fb.Opts(max_steps=1))
+        E.synchronize()
+        fb.profile_enable(False)
+        ms, n = fb.profile_read()
+        st = E.state()
+        E.close()
+        assert (st["steps"] == 1).all() and (st["status"] == fb.MAXSTEPS).all()
+        n_sys, n_bodies = int(nb.shape[0]), int(nb.sum())
+        nbytes = n_bodies * (104 + 96) + n_sys * (68 + 36)
+        avg = ms / 1e3 / max(n, 1)
+        out[f"{n_sys}x3"] = {"kernel": "k_plain_spl<3>, zero steps", "bytes_per_launch": nbytes,
+                             "kernel_avg_ms": avg * 1e3, "launches": n, "achieved_gbps": nbytes / avg / 1e9,
+                             "peak_gbps": HBM_PEAK_GBPS, "frac": nbytes / avg / 1e9 / HBM_PEAK_GBPS}
+    return out
 
 
 def timed(fb, torch, ens, fn):
@@ -164,17 +234,27 @@ def lifetimes_extras(fb, gen, torch, log, orbits=100.0, quantum=2000):
     close-encounter and ejection rules, on a bounded horizon of `orbits`
     inner orbits (the workload's 1e4 orbits would take hours).  Plain: one
     launch per bucket, retired lanes idle until their wave's last system
-    ends; persistent: quanta with in-kernel compaction of retired systems."""
+    ends; persistent: quanta with in-kernel compaction of retired systems
+    (the fused-kernel class chosen automatically: system-per-lane while the
+    survivors fill the device, then body-per-lane; and, for comparison, the
+    body-per-lane class throughout)."""
     import numpy as np
     ens, p = gen.workload("lifetimes_65536x4-8")
     t_end = 2 * math.pi * orbits
     base = dict(adaptive=True, eta=p["eta"], stop_rules=3, r_eject=p["r_eject"])
     out = {"workload": f"lifetimes_65536x4-8: {ens.n_sys} systems, n uniform 4..8, adaptive eta={p['eta']}, "
                        f"stop rules, bounded horizon t = 2pi*{orbits:g} (workload horizon 2pi*1e4)"}
-    for name, opts in [("plain", fb.Opts(**base)),
-                       ("persistent_compact", fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=quantum,
-                                                      compact=True, **base))]:
-        dt, st = timed(fb, torch, ens, lambda E: E.integrate(t_end, 0.0, opts))
+    pers = fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=quantum, compact=True, **base)
+    saved = fb.get_plan(0)
+    for name, opts, cls in [("plain", fb.Opts(**base), None),
+                            ("persistent_compact", pers, None),
+                            ("persistent_compact_body_per_lane_class", pers, fb.MAP_BPL)]:
+        if cls is not None:
+            fb.set_plan(0, cls, saved[1], saved[2])
+        try:
+            dt, st = timed(fb, torch, ens, lambda E: E.integrate(t_end, 0.0, opts))
+        finally:
+            fb.set_plan(0, *saved)
         useful = float(st["steps"].sum())
         flops = float(sum(flops_per_system_step(int(n)) * float(k) for n, k in zip(ens.n_body, st["steps"])))
         hist = {str(k): int(v) for k, v in zip(*np.unique(st["status"], return_counts=True))}
@@ -400,8 +480,10 @@ def main():
                     help="Hermite steps per benchmark step (the workload's 100000)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--extras", action="store_true",
-                    help="also run the ragged (autotuned, plain vs persistent) and uneven-lifetimes "
-                         "(plain vs compaction) comparisons")
+                    help="also run every other extra workload (paper ICs, MVS, Runge-Kutta, large n, logging)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the ragged (autotuned, plain vs persistent) and uneven-lifetimes "
+                         "(plain vs compaction) comparisons that run by default")
     ap.add_argument("--extra", action="append", default=[],
                     choices=["ragged", "lifetimes", "paper_ics", "mvs", "rkck", "large_n", "logging",
                              "table1"],
@@ -475,14 +557,17 @@ def main():
     fb.profile_read()
     fb.profile_enable(True)
     torch.cuda.synchronize()
+    per_launch_ms = []
     t0 = time.perf_counter()
     for k in range(args.steps):
         energy = one_step()
+        ms_k, n_k = fb.profile_read()   # this step's launch (the step has synchronised)
+        per_launch_ms.append(ms_k / max(n_k, 1))
         print(f"[bench] step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fb.profile_enable(False)
-    kernel_ms, launches = fb.profile_read()
+    kernel_ms, launches = sum(per_launch_ms), len(per_launch_ms)
     assert np.all(np.isfinite(energy))
 
     sys_steps = ens.n_sys * K * args.steps
@@ -492,9 +577,20 @@ def main():
     achieved = flops_per_launch / kern_avg_s / 1e12
     m, w, _ = fb.get_plan(3)
     probe = fb.fp64_fma_ceiling()
-    counters = MEASURED_COUNTERS.get(kernel_source_hash())
-    counter_tflops = (counters["fp64_flops_per_system_step"] * ens.n_sys * K / kern_avg_s / 1e12
-                      if counters else None)
+    src_hash = kernel_source_hash()
+    counters = PROFILED_COUNTERS.get(src_hash)
+    profiled = None
+    if counters:
+        profiled = dict(counters, source=PROFILE_SUMMARY, kernel_source=src_hash,
+                        note="hardware counters of a rocprofv3 run of this kernel source on another box "
+                             "(records, not measured in this run)",
+                        counter_tflops_at_this_runs_time=counters["fp64_flops_per_system_step"] * ens.n_sys * K
+                        / kern_avg_s / 1e12)
+    half = max(1, len(per_launch_ms) // 4)
+    sustained = {"per_launch_ms": per_launch_ms,
+                 "first_quarter_avg_ms": sum(per_launch_ms[:half]) / half,
+                 "last_quarter_avg_ms": sum(per_launch_ms[-half:]) / half}
+    sustained["last_over_first"] = sustained["last_quarter_avg_ms"] / sustained["first_quarter_avg_ms"]
     result = {
         "metric": METRIC,
         "value": value,
@@ -515,18 +611,21 @@ def main():
                    "waves_per_group": w},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
+                     "traffic": MEASURED_TRAFFIC.get(src_hash),
                      "kernel": "k_plain_spl<3>", "kernel_avg_ms": kern_avg_s * 1e3,
                      "kernel_launches": launches,
                      "flops_per_launch": flops_per_launch,
                      "fma_probe_tflops": probe, "frac_of_fma_probe": achieved / probe if probe else None,
-                     "counter_tflops": counter_tflops, "counters": counters},
+                     "fma_probe_clock_ghz_lower_bound": probe / (256 * 128 * 1e-3) if probe else None,
+                     "sustained": sustained, "profiled": profiled},
         "pair_interactions_per_s": value * 2 * 3,
     }
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
     extras = {}
+    restore_plans()
+    result["roofline"]["load_store"] = load_store_probe(fb, ens, h)
     restore_plans()
     if not args.no_serve:
         rep = serving_report(fb, gen, log, args.serve_requests, args.serve_max_resident, args.serve_quantum,
@@ -544,10 +643,15 @@ def main():
         ("large_n", lambda: large_n_extras(fb, gen, torch, log)),
         ("logging", lambda: logging_extras(fb, gen, torch, log)),
     ]
+    default_runs = () if args.no_compare else ("ragged", "lifetimes")
     for name, fn in runs:
-        if args.extras or name in args.extra:
+        if args.extras or name in args.extra or name in default_runs:
             extras[name] = fn()
             restore_plans()
+    if "ragged" in extras:
+        result["ragged_persistent_over_plain"] = extras["ragged"]["persistent_over_plain"]
+    if "lifetimes" in extras:
+        result["lifetimes_compaction_over_plain"] = extras["lifetimes"]["compaction_over_plain"]
     if "table1" in args.extra:
         extras["table1"] = table1_extras(fb, gen, torch, log, tau=args.table1_tau)
     if extras:

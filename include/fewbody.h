@@ -349,7 +349,7 @@ fb_status fb_hermite_steps_device(int32_t n_sys, int32_t n, const double *d_mass
 /* ---------------------------------------------------------------- plans */
 /* The launch plan of body count n: lane mapping (FB_MAP_*) and waves per
  * workgroup (1..4) of its plain launches.  System-per-lane is built for
- * n <= 10 (n <= 5 with adaptive steps or stop rules); FB_MAP_AUTO (the
+ * n <= 10 (n <= 8 with adaptive steps or stop rules); FB_MAP_AUTO (the
  * default) picks it for a bucket whose 64-system tiles give every SIMD of
  * the device a wavefront, and body-per-lane otherwise.  Entry n = 0 is the
  * fused persistent launch: its mapping selects the kernel class

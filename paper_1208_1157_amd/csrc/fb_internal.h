@@ -23,7 +23,7 @@ enum Mapping { MAP_SPL = 1, MAP_BPL = 2 };
 constexpr int kMaxBodies = 16;         // kernels specialised per n exist for n <= 16
 constexpr int kMaxLargeBodies = 512;   // larger systems run the runtime-n large-n kernels
 constexpr int kMaxSplBodies = 10;      // plain system-per-lane instances exist for n <= 10
-constexpr int kMaxSplAdv = 5;          // ... with adaptive steps / stop rules for n <= 5
+constexpr int kMaxSplAdv = 8;          // ... with adaptive steps / stop rules for n <= 8
 constexpr int kMaxSplPersistent = 0;   // the body-per-lane fused class runs no system-per-lane tiles
 constexpr int kMaxMvsBodies = 8;       // MVS kernels (system per lane) exist for n <= 8
 

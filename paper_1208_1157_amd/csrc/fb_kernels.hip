@@ -144,10 +144,17 @@ struct BplLds {
 #define FB_SPL_LDS_MIN 6
 #endif
 
+// Rows parked after the bases by the adaptive step loop (n <= kMaxSplAdv):
+// the step size and the system's clock (t, t_end, carried step, run steps,
+// steps, status, last step).
+constexpr int kSplParkClock = 8;
+
 // LDS bytes per wavefront a system-per-lane step of n bodies uses.
 __host__ __device__ constexpr size_t spl_lds_bytes(int n)
 {
-    return n >= FB_SPL_LDS_MIN ? (size_t)6 * n * 64 * sizeof(double) : 0;
+    return n >= FB_SPL_LDS_MIN
+               ? (size_t)(6 * n + (n <= kMaxSplAdv ? kSplParkClock : 0)) * 64 * sizeof(double)
+               : 0;
 }
 
 // Per-wavefront LDS stride of the system-per-lane fused class, whose waves
@@ -155,6 +162,8 @@ __host__ __device__ constexpr size_t spl_lds_bytes(int n)
 // for the body-per-lane slice and for the largest parked bases.
 constexpr size_t kWideLdsStride = 6 * kMaxSplBodies * 64 * sizeof(double);
 static_assert(kWideLdsStride >= sizeof(BplLds), "wide LDS stride too small");
+static_assert(kWideLdsStride >= spl_lds_bytes(kMaxSplAdv) &&
+                  kWideLdsStride >= spl_lds_bytes(kMaxSplBodies), "wide LDS stride too small");
 
 // This wavefront's slice of its workgroup's dynamic LDS, reached through
 // the module-level symbol (not a pointer argument) so separately compiled
@@ -320,6 +329,10 @@ __device__ __forceinline__ void spl_pair(const int i, const int j, const double 
     if (TS) {
         const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
         wmax = fmax(wmax, fma(al, ru, u2) * ri2);
+        // Keep the running maximum a serial chain through the pairs: left
+        // free, the compiler rebalances it into a tree at the end, which
+        // keeps every pair's inputs live and spills systems of n >= 6.
+        __asm__ __volatile__("" : "+v"(wmax));
     }
 }
 
@@ -357,18 +370,28 @@ __device__ __forceinline__ void spl_accjerk(const double (&m)[N], const double (
     }
 }
 
+// This lane's parking area: [6N + kSplParkClock][64] doubles, lane fastest.
+template <int N, bool WIDE>
+__device__ __forceinline__ double *spl_park()
+{
+    return reinterpret_cast<double *>(wave_lds_base<spl_lds_bytes(N), WIDE>()) + (threadIdx.x & 63);
+}
+
 // One P(EC)^2 step of size h.  On entry (a, jk) hold the carried a0, j0; on
 // exit (x, v) are the corrected state and (a, jk) the last evaluation.
-// Returns the step-rule quantity of the last evaluation (TS only).
-template <int N, bool TS, bool WIDE>
+// Returns the step-rule quantity of the last evaluation (TS only).  With
+// RELOAD (parked steps only) the caller has parked h in row 6N and the step
+// coefficients are rebuilt from it after each evaluation instead of being
+// kept in registers through it.
+template <int N, bool TS, bool WIDE, bool RELOAD = false>
 __device__ __forceinline__ double spl_step(const double (&m)[N], double (&x)[N][3],
                                            double (&v)[N][3], double (&a)[N][3],
-                                           double (&jk)[N][3], const Coef &k)
+                                           double (&jk)[N][3], const Coef &k0)
 {
     constexpr bool kPark = N >= FB_SPL_LDS_MIN;
-    // this wavefront's parking area: [6N][64] doubles, lane fastest
-    double *park = reinterpret_cast<double *>(wave_lds_base<spl_lds_bytes(N), WIDE>()) +
-                   (threadIdx.x & 63);
+    static_assert(!RELOAD || kPark, "coefficient reload needs the parking area");
+    double *park = spl_park<N, WIDE>();
+    Coef k = k0;
     double bx[N][3], bv[N][3], xc[N][3], vc[N][3];
 #pragma unroll
     for (int b = 0; b < N; ++b)
@@ -390,6 +413,8 @@ __device__ __forceinline__ double spl_step(const double (&m)[N], double (&x)[N][
     spl_accjerk<N, false>(m, xc, vc, a, jk, w);
     if (kPark)
         __asm__ __volatile__("" ::: "memory");
+    if (RELOAD)
+        k = make_coef(park[6 * N * 64]);
 #pragma unroll
     for (int b = 0; b < N; ++b)
 #pragma unroll
@@ -405,6 +430,8 @@ __device__ __forceinline__ double spl_step(const double (&m)[N], double (&x)[N][
     spl_accjerk<N, TS>(m, xc, vc, a, jk, w);
     if (kPark)
         __asm__ __volatile__("" ::: "memory");
+    if (RELOAD)
+        k = make_coef(park[6 * N * 64]);
 #pragma unroll
     for (int b = 0; b < N; ++b)
 #pragma unroll
@@ -561,12 +588,38 @@ __device__ __forceinline__ void spl_run(const Bucket &B, const int slot, const S
                 c.status = ST_MAXSTEPS;
         }
     } else {
+        // Parked steps also park the step size and the clock across the step
+        // (rows 6N..6N+7), so the evaluations keep only the system in VGPRs.
+        constexpr bool kParkClock = N >= FB_SPL_LDS_MIN;
+        double *pc = kParkClock ? spl_park<N, WIDE>() + 6 * N * 64 : nullptr;
         for (int q = 0; q < P.quantum; ++q) {
             double h = 0.0;
             bool last = false;
             if (!plan_step(c, P, h, last))
                 break;
-            const double w = spl_step<N, true, WIDE>(m, x, v, a, jk, make_coef(h));
+            if constexpr (kParkClock) {
+                pc[0] = h;
+                pc[64] = c.t;
+                pc[2 * 64] = c.t_end;
+                pc[3 * 64] = c.dtn;
+                pc[4 * 64] = __longlong_as_double(c.k);
+                pc[5 * 64] = __longlong_as_double(c.steps);
+                pc[6 * 64] = (double)c.status;
+                pc[7 * 64] = last ? 1.0 : 0.0;
+                __asm__ __volatile__("" ::: "memory");
+            }
+            const double w = spl_step<N, true, WIDE, kParkClock>(m, x, v, a, jk, make_coef(h));
+            if constexpr (kParkClock) {
+                __asm__ __volatile__("" ::: "memory");
+                h = pc[0];
+                c.t = pc[64];
+                c.t_end = pc[2 * 64];
+                c.dtn = pc[3 * 64];
+                c.k = __double_as_longlong(pc[4 * 64]);
+                c.steps = __double_as_longlong(pc[5 * 64]);
+                c.status = (int)pc[6 * 64];
+                last = pc[7 * 64] != 0.0;
+            }
             double dtp = P.adaptive == 2 ? paper_dt<N>(a, jk, P.eta) : P.eta * rsqrt_nr(w);
             finish_step(c, P, last, h, dtp);
             const int fl = spl_stop_flags<N>(m, x, v, P);
@@ -921,9 +974,9 @@ __device__ __noinline__ bool bpl_tile(const Bucket &B, const Tile &T, const int 
 }
 
 // Tile dispatch.  The body-per-lane class (SPLC false) keeps the fused
-// kernel at <= 128 VGPRs (4 waves per SIMD) and runs every tile body-per-
+// kernel at <= 168 VGPRs (3 waves per SIMD) and runs every tile body-per-
 // lane; the system-per-lane class gives the kernel the full register file
-// (1 wave per SIMD) and runs system-per-lane tiles up to n = 10 (n = 5 with
+// (1 wave per SIMD) and runs system-per-lane tiles up to n = 10 (n = 8 with
 // adaptive steps / stop rules), body-per-lane beyond.
 template <bool ADV, bool SPLC>
 __device__ __forceinline__ bool run_tile(const Bucket &B, const Tile &T, const int *list,
@@ -938,13 +991,13 @@ __device__ __forceinline__ bool run_tile(const Bucket &B, const Tile &T, const i
             case 3: return spl_tile<3, ADV>(B, T, list, P, slot);
             case 4: return spl_tile<4, ADV>(B, T, list, P, slot);
             case 5: return spl_tile<5, ADV>(B, T, list, P, slot);
+            case 6: return spl_tile<6, ADV>(B, T, list, P, slot);
+            case 7: return spl_tile<7, ADV>(B, T, list, P, slot);
+            case 8: return spl_tile<8, ADV>(B, T, list, P, slot);
             default: break;
             }
             if constexpr (!ADV) {
                 switch (n) {
-                case 6: return spl_tile<6, false>(B, T, list, P, slot);
-                case 7: return spl_tile<7, false>(B, T, list, P, slot);
-                case 8: return spl_tile<8, false>(B, T, list, P, slot);
                 case 9: return spl_tile<9, false>(B, T, list, P, slot);
                 case 10: return spl_tile<10, false>(B, T, list, P, slot);
                 default: break;
@@ -3365,6 +3418,9 @@ hipError_t launch_plain(const Bucket &B, int mapping, int waves_per_group, const
             case 3: FB_LA(3); break;
             case 4: FB_LA(4); break;
             case 5: FB_LA(5); break;
+            case 6: FB_LA(6); break;
+            case 7: FB_LA(7); break;
+            case 8: FB_LA(8); break;
             default: return hipErrorInvalidValue;
             }
         } else {

@@ -459,34 +459,21 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     const int W = std::max(1, std::min(4, p0.waves_per_group));
     const bool adv = o.adaptive || o.stop_rules;
     const int quantum = o.steps_per_quantum > 0 ? o.steps_per_quantum : INT_MAX;
-    const int cls = persistent_class(p0, small, adv, e->num_cu);
-    const int spl_lim = persistent_spl_limit(cls, adv ? 1 : 0);
-    int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
-    const int occ = persistent_max_groups_per_cu(adv ? 1 : 0, cls, W);
-    if (occ > 0)
-        gpc = std::min(gpc, occ);
-    const int grid = std::max(1, gpc * e->num_cu);
     const StepParams P = make_params(o, quantum);
+    const bool compact = o.compact != 0;
+    int cls = persistent_class(p0, small, adv, e->num_cu);
 
-    // mapping per bucket, tile order (the small buckets), initial lists
-    // (identity) and counts
-    std::vector<int> mapping(nbk, MAP_BPL), counts(nbk, 0), order, ident;
+    // Lists (identity) and counts of every bucket; mapping and tile order of
+    // the small buckets.
+    std::vector<int> counts(nbk, 0), order, ident;
     for (int i = n_large; i < nbk; ++i) {
-        const int n = e->buckets[i].n;
         order.push_back(i);
-        const int m = get_plan(n).mapping;
-        // in the system-per-lane class every bucket that can runs system-per-lane,
-        // unless its plan asks for body-per-lane
-        mapping[i] = (n <= spl_lim && m != MAP_BPL && (m == MAP_SPL || cls == 1)) ? MAP_SPL
-                                                                                 : MAP_BPL;
         counts[i] = e->buckets[i].count;
     }
     ident.reserve(e->L.list_total);
     for (const Bucket &B : e->buckets)
         for (int s = 0; s < B.pitch; ++s)
             ident.push_back(s);
-    FB_HIP(hipMemcpyAsync(e->d_mapping, mapping.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
-                          e->stream));
     if (nb_small)
         FB_HIP(hipMemcpyAsync(e->d_order, order.data(), sizeof(int) * nb_small,
                               hipMemcpyHostToDevice, e->stream));
@@ -494,7 +481,32 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                           hipMemcpyHostToDevice, e->stream));
     FB_HIP(hipMemcpyAsync(e->d_counts[0], counts.data(), sizeof(int) * nbk, hipMemcpyHostToDevice,
                           e->stream));
-    FB_HIP(hipStreamSynchronize(e->stream));   // host vectors die at return
+    std::vector<int> mapping(nbk, MAP_BPL);
+    int grid = 1;
+    // Per-bucket mappings and grid of fused-kernel class c.
+    auto set_class = [&](int c) -> hipError_t {
+        const int spl_lim = persistent_spl_limit(c, adv ? 1 : 0);
+        for (int i = n_large; i < nbk; ++i) {
+            const int n = e->buckets[i].n;
+            const int m = get_plan(n).mapping;
+            // in the system-per-lane class every bucket that can runs system-
+            // per-lane, unless its plan asks for body-per-lane
+            mapping[i] = (n <= spl_lim && m != MAP_BPL && (m == MAP_SPL || c == 1)) ? MAP_SPL
+                                                                                   : MAP_BPL;
+        }
+        int gpc = p0.groups_per_cu > 0 ? p0.groups_per_cu : 8;
+        const int occ = persistent_max_groups_per_cu(adv ? 1 : 0, c, W);
+        if (occ > 0)
+            gpc = std::min(gpc, occ);
+        grid = std::max(1, gpc * e->num_cu);
+        cls = c;
+        hipError_t err = hipMemcpyAsync(e->d_mapping, mapping.data(), sizeof(int) * nbk,
+                                        hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)   // the host vector is rewritten by the next switch
+            err = hipStreamSynchronize(e->stream);
+        return err;
+    };
+    FB_HIP(set_class(cls));   // also waits for the copies above (host vectors die at return)
 
     ActiveLists AL[2];
     for (int k = 0; k < 2; ++k) {
@@ -506,7 +518,6 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
     }
     int *d_ntiles = e->d_ints + 1, *d_head = e->d_ints + 2;
 
-    const bool compact = o.compact != 0;
     // Enqueue one quantum.  With compaction it reads lists/counts [k] and
     // writes the survivors to [1-k]; without, every quantum re-runs the
     // identity lists [0] (retired systems exit at once).
@@ -540,22 +551,32 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
         FB_HIP(hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    FB_HIP(hipStreamBeginCapture(e->capture_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t cerr = quantum_launch(e->capture_stream, 0);
-    if (cerr == hipSuccess)
-        cerr = quantum_launch(e->capture_stream, 1);
-    hipError_t eerr = hipStreamEndCapture(e->capture_stream, &graph);
-    if (cerr != hipSuccess)
-        return hip_fail(cerr, "quantum capture");
-    FB_HIP(eerr);
-    hipError_t ierr = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ierr != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return hip_fail(ierr, "hipGraphInstantiate");
-    }
-    fb_status result = FB_OK;
+    auto release = [&]() {
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto capture = [&]() -> fb_status {
+        release();
+        FB_HIP(hipStreamBeginCapture(e->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t cerr = quantum_launch(e->capture_stream, 0);
+        if (cerr == hipSuccess)
+            cerr = quantum_launch(e->capture_stream, 1);
+        hipError_t eerr = hipStreamEndCapture(e->capture_stream, &graph);
+        if (cerr != hipSuccess)
+            return hip_fail(cerr, "quantum capture");
+        FB_HIP(eerr);
+        hipError_t ierr = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ierr != hipSuccess)
+            return hip_fail(ierr, "hipGraphInstantiate");
+        return FB_OK;
+    };
+    fb_status result = capture();
     long long done_steps = 0;
-    for (;;) {
+    while (result == FB_OK) {
         {
             ProfScope ps(e->stream);
             hipError_t err = hipGraphLaunch(exec, e->stream);
@@ -570,7 +591,7 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                 break;
             continue;
         }
-        long long act = 0;
+        long long act = 0, spl_tiles = 0;
         if (compact) {
             // survivors of the second quantum sit in counts[0] (the small
             // buckets' entries; at most kMaxBodies - 1 of them)
@@ -584,8 +605,10 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                 result = hip_fail(err, "active count");
                 break;
             }
-            for (int i = 0; i < nb_small; ++i)
+            for (int i = 0; i < nb_small; ++i) {
                 act += e->h_pinned[8 + i];
+                spl_tiles += (e->h_pinned[8 + i] + 63) / 64;
+            }
             if (n_large) {   // the large buckets keep no survivor lists
                 FB_HIP(launch_reset_counter(e->d_ints + 3, 1, e->stream));
                 for (int i = 0; i < n_large; ++i)
@@ -604,9 +627,21 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
         }
         if (act == 0)
             break;
+        // The system-per-lane class runs one wavefront per SIMD; once the
+        // survivors' 64-system tiles no longer give every SIMD one, the body-
+        // per-lane class (a system over n lanes) keeps more of the device
+        // busy.  The two classes compute bitwise the same states, so the
+        // switch is invisible in the results.
+        if (compact && cls == 1 && p0.mapping == 0 && spl_tiles < 4LL * e->num_cu) {
+            hipError_t err = set_class(0);
+            if (err != hipSuccess) {
+                result = hip_fail(err, "class switch");
+                break;
+            }
+            result = capture();
+        }
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    release();
     return result;
 }
 

@@ -304,7 +304,7 @@ def test_invalid_device_inputs_rejected(fb):
 def _adaptive_case(plans, ora, mapping, n_sys, orbits):
     fb = plans
     for n in range(4, 9):
-        use_spl = mapping == "spl" and n <= 6
+        use_spl = mapping == "spl" and n <= 8
         fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
     ens, p = gen.workload("lifetimes_65536x4-8", n_sys=n_sys)
     t_end = 2 * math.pi * orbits
@@ -358,7 +358,7 @@ def test_paper_step_rule_parity(plans, ora, mapping):
     mix, 5 inner orbits: same step counts as the oracle and parity to 1e-10."""
     fb = plans
     for n in range(2, 17):
-        use_spl = mapping == "spl" and n <= 6
+        use_spl = mapping == "spl" and n <= 8
         fb.set_plan(n, fb.MAP_SPL if use_spl else fb.MAP_BPL, 2)
     parts = [gen.paper_ics(4, n) for n in (3, 4, 5, 6)] + [gen.ragged_hill(40, seed=8, n_lo=3, n_hi=12)]
     nb = np.concatenate([p.n_body for p in parts])

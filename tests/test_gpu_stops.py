@@ -62,7 +62,7 @@ def plunging_ensemble():
 def test_stalled_dt_and_max_steps_match_the_oracle(plans, ora, sched, mapping):
     fb = plans
     for n in range(2, 17):
-        fb.set_plan(n, fb.MAP_SPL if mapping == "spl" and n <= 5 else fb.MAP_BPL, 2)
+        fb.set_plan(n, fb.MAP_SPL if mapping == "spl" and n <= 8 else fb.MAP_BPL, 2)
     fb.set_plan(0, fb.MAP_SPL if mapping == "spl" else fb.MAP_BPL, 2, 8)
     ens = plunging_ensemble()
     t_end, eta, cap = 1e4, 0.01, 3000
