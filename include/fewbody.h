@@ -346,6 +346,20 @@ fb_status fb_hermite_steps_device(int32_t n_sys, int32_t n, const double *d_mass
                                   double *d_pos, double *d_vel, int32_t *d_status,
                                   int64_t n_steps, double dt, void *d_workspace,
                                   size_t ws_bytes, void *hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * fb_hermite_steps_device without a workspace.  The packed state lives in a
+ * fixed 64 MiB array the library holds on each device it runs on until the
+ * process ends (about 170000 three-body or 38000 sixteen-body systems);
+ * larger batches fail with FB_E_NOMEM.  The call allocates nothing and
+ * synchronises nothing.  Every call on one device shares that array: calls
+ * whose work overlaps on one device (other streams, other threads) race and
+ * must be serialised by the caller; work on one stream is ordered. */
+fb_status fb_hermite_steps_device_noalloc(int32_t n_sys, int32_t n, const double *d_mass,
+                                          double *d_pos, double *d_vel, int32_t *d_status,
+                                          int64_t n_steps, double dt, void *hip_stream);
+
 /* ---------------------------------------------------------------- plans */
 /* The launch plan of body count n: lane mapping (FB_MAP_*) and waves per
  * workgroup (1..4) of its plain launches.  System-per-lane is built for

@@ -7,7 +7,8 @@
 // same kernels an ensemble uses (Eq. 3 predictor, Eq. 4 corrector twice per
 // step as in Algorithm 2), and unpacked back in place.  Nothing is read back
 // to the host and nothing outlives the call, so the call is pure stream
-// work.  The bucket lives in a caller workspace.
+// work.  The bucket lives either in a caller workspace or, for callers that
+// cannot allocate device memory, in a fixed per-device array of this file.
 #include "fewbody.h"
 #include "fb_internal.h"
 #include "fb_runtime_internal.h"
@@ -16,11 +17,25 @@
 
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 using namespace fb;
 using namespace fb::rt;
 
 namespace {
+
+// Largest batch the allocation-free entry point takes: bucket, tables and
+// flag of, e.g., 131072 three-body or 38000 sixteen-body systems.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+
+// The allocation-free entry point's bucket.  Host code never uses this name
+// as an address: every device gets its own copy, whose address is looked up
+// once per device (g_scratch_ptr).
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices];
 
 // Batches above this many systems are rejected before any size arithmetic.
 constexpr int32_t kMaxSoloSystems = 1 << 26;
@@ -141,6 +156,29 @@ fb_status solo_run(char *base, const SoloLayout &L, const double *d_mass, double
     return FB_OK;
 }
 
+// This device's copy of `scratch`, looked up on the first call on the device
+// (with the device current) and kept for the process.
+fb_status device_scratch(char *&out)
+{
+    int dev = 0;
+    FB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(FB_E_DEVICE, "device %d is beyond the %d devices the static scratch serves",
+                    dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256)
+            return fail(FB_E_DEVICE, "static scratch at an unusable address");
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    out = g_scratch_ptr[dev];
+    return FB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -161,6 +199,29 @@ fb_status fb_hermite_steps_device(int32_t n_sys, int32_t n, const double *d_mass
         return fail(FB_E_INVAL, "workspace must be 256-byte aligned");
     return solo_run(static_cast<char *>(d_workspace), L, d_mass, d_pos, d_vel, d_status, n_steps,
                     dt, (hipStream_t)hip_stream, true);
+}
+
+fb_status fb_hermite_steps_device_noalloc(int32_t n_sys, int32_t n, const double *d_mass,
+                                          double *d_pos, double *d_vel, int32_t *d_status,
+                                          int64_t n_steps, double dt, void *hip_stream)
+{
+    SoloLayout L;
+    fb_status st = solo_check(n_sys, n, d_mass, d_pos, d_vel, n_steps, dt, L);
+    if (st != FB_OK)
+        return st;
+    if (n_sys == 0)
+        return FB_OK;
+    if (L.total > kScratchBytes)
+        return fail(FB_E_NOMEM,
+                    "%d systems of %d bodies need %zu bytes; the static scratch holds %zu "
+                    "(use fb_hermite_steps_device with a workspace)",
+                    n_sys, n, L.total, kScratchBytes);
+    char *base = nullptr;
+    st = device_scratch(base);
+    if (st != FB_OK)
+        return st;
+    return solo_run(base, L, d_mass, d_pos, d_vel, d_status, n_steps, dt,
+                    (hipStream_t)hip_stream, false);
 }
 
 size_t fb_hermite_steps_workspace_bytes(int32_t n_sys, int32_t n)

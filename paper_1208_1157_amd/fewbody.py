@@ -90,6 +90,7 @@ _SIGS = {
                                            ctypes.POINTER(_p)]),
     "fb_hermite_steps_workspace_bytes": (_sz, [_i32, _i32]),
     "fb_hermite_steps_device": (ctypes.c_int, [_i32, _i32, _p, _p, _p, _p, _i64, _d, _p, _sz, _p]),
+    "fb_hermite_steps_device_noalloc": (ctypes.c_int, [_i32, _i32, _p, _p, _p, _p, _i64, _d, _p]),
     "fb_eval_rsqrt": (ctypes.c_int, [_p, _p, _i64, _p]),
     "fb_integrate_steps": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
     "fb_integrate_mvs": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(FbOpts)]),
@@ -216,12 +217,13 @@ def eval_rsqrt(x):
     return out
 
 
-def hermite_steps_device(n, mass, pos, vel, n_steps, dt, status=None, workspace=None):
+def hermite_steps_device(n, mass, pos, vel, n_steps, dt, status=None, noalloc=False, workspace=None):
     """n_steps fixed Hermite steps of the systems of n bodies held in float64
     CUDA tensors mass [N], pos/vel [N, 3] (N = n_sys * n), in place, on
-    torch's current stream (fb_hermite_steps_device).  status: optional int32
+    torch's current stream (fb_hermite_steps_device, or with noalloc the
+    allocation-free fb_hermite_steps_device_noalloc).  status: optional int32
     CUDA tensor [n_sys] for the systems' FB_SYS_* codes.  workspace: optional
-    uint8 CUDA tensor (allocated here when None)."""
+    uint8 CUDA tensor (allocated here when None and noalloc is False)."""
     import torch
     for t_ in (mass, pos, vel):
         if not (isinstance(t_, torch.Tensor) and t_.is_cuda and t_.dtype == torch.float64
@@ -235,6 +237,10 @@ def hermite_steps_device(n, mass, pos, vel, n_steps, dt, status=None, workspace=
                                    and status.numel() == n_sys):
         raise FewbodyError(E_INVAL, "status must be an int32 CUDA tensor of n_sys entries")
     sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if noalloc:
+        _check(_lib.fb_hermite_steps_device_noalloc(n_sys, int(n), _ptr(mass), _ptr(pos), _ptr(vel),
+                                                    _ptr(status), int(n_steps), float(dt), sp))
+        return
     ws = int(_lib.fb_hermite_steps_workspace_bytes(n_sys, int(n)))
     if ws == 0 and n_sys > 0:
         raise FewbodyError(E_INVAL, "invalid batch shape")
