@@ -696,7 +696,10 @@ __device__ __forceinline__ void bpl_interact(const BplLds &L, const int idx,
 // ascending order, then the star (the star lane sums planets 1..n-1), so the
 // star's contribution is added last.  Branch-free: the n-2 planet partners
 // skip this lane's own index arithmetically and the last partner is peeled.
-template <int N, bool TS>
+// ILP unrolls the partner loop fully (the full-register-file kernel class,
+// where a wave has its SIMD to itself and needs independent interactions
+// in flight); the accumulation order is the same either way.
+template <int N, bool TS, bool ILP = false>
 __device__ __forceinline__ void bpl_eval(BplLds &L, const int lane, const int b, const int s,
                                          const double (&xi)[3], const double (&vi)[3],
                                          double (&a)[3], double (&jk)[3], double &wmax)
@@ -712,10 +715,18 @@ __device__ __forceinline__ void bpl_eval(BplLds &L, const int lane, const int b,
         jk[c] = 0.0;
     }
     const int skip = b == 0 ? (1 << 20) : b;
+    if constexpr (ILP) {
+#pragma unroll
+        for (int k = 0; k < N - 2; ++k) {
+            const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
+            bpl_interact<TS>(L, j * S + s, xi, vi, a, jk, wmax);
+        }
+    } else {
 #pragma unroll FB_BPL_UNROLL
-    for (int k = 0; k < N - 2; ++k) {
-        const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
-        bpl_interact<TS>(L, j * S + s, xi, vi, a, jk, wmax);
+        for (int k = 0; k < N - 2; ++k) {
+            const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
+            bpl_interact<TS>(L, j * S + s, xi, vi, a, jk, wmax);
+        }
     }
     bpl_interact<TS>(L, (b == 0 ? N - 1 : 0) * S + s, xi, vi, a, jk, wmax);
     wave_sync();
@@ -764,7 +775,7 @@ __device__ __forceinline__ int sys_or(BplLds &L, int lane, int s, int v)
     return r;
 }
 
-template <int N>
+template <int N, bool ILP = false>
 __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const int b,
                                               const int s, const double mi, const double (&x)[3],
                                               const double (&v)[3], const StepParams &P)
@@ -785,8 +796,7 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
             fl |= 4;
         if (P.stop_rules & 1) {
             const double inv24m0 = 1.0 / (24.0 * L.m[s]);
-#pragma unroll 1
-            for (int k = 0; k < N - 2; ++k) {
+            auto hill = [&](const int k) {
                 const int idx = planet_partner(k, b) * S + s;
                 const double2 q0 = L.xy[idx];
                 const double2 q1 = L.zvx[idx];
@@ -794,6 +804,15 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
                 const double sep2 = fma(ez, ez, fma(ey, ey, ex * ex));
                 if (hill_close(sep2, mi, L.m[idx], inv24m0, rb, L.red[idx]))
                     fl |= 2;
+            };
+            if constexpr (ILP) {
+#pragma unroll
+                for (int k = 0; k < N - 2; ++k)
+                    hill(k);
+            } else {
+#pragma unroll 1
+                for (int k = 0; k < N - 2; ++k)
+                    hill(k);
             }
         }
     }
@@ -851,11 +870,11 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
         for (int cc = 0; cc < 3; ++cc)
             predict_comp(k, x[cc], v[cc], a0[cc], j0[cc], xc[cc], vc[cc], bx[cc], bv[cc]);
         double w = 0.0;
-        bpl_eval<N, false>(L, lane, b, s, xc, vc, ak, jk, w);
+        bpl_eval<N, false, WIDE>(L, lane, b, s, xc, vc, ak, jk, w);
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
             correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
-        bpl_eval<N, ADV>(L, lane, b, s, xc, vc, ak, jk, w);
+        bpl_eval<N, ADV, WIDE>(L, lane, b, s, xc, vc, ak, jk, w);
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
             correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
@@ -878,7 +897,7 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
             finish_step(c, P, last, h, dtp);
         }
         if (ADV) {
-            const int fl = bpl_stop_flags<N>(L, lane, b, s, mi, x, v, P);
+            const int fl = bpl_stop_flags<N, WIDE>(L, lane, b, s, mi, x, v, P);
             if (act && fl)
                 c.status = status_of_flags(fl);
         }

@@ -408,6 +408,14 @@ fb_status count_active(fb_ensemble *e, int &out)
     return FB_OK;
 }
 
+// Waves per SIMD below which the survivors of a compacted persistent run
+// (automatic class) move to the full-register kernel class with body-per-
+// lane tiles and unrolled partner loops: one wave per SIMD, more work in
+// flight per wave.
+#ifndef FB_TAIL_WAVES_PER_SIMD
+#define FB_TAIL_WAVES_PER_SIMD 2
+#endif
+
 // Plain schedule: one launch per bucket (one per quantum if quanta are set).
 fb_status run_plain(fb_ensemble *e, const fb_opts &o, long long step_bound)
 {
@@ -483,9 +491,11 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                           e->stream));
     std::vector<int> mapping(nbk, MAP_BPL);
     int grid = 1;
-    // Per-bucket mappings and grid of fused-kernel class c.
-    auto set_class = [&](int c) -> hipError_t {
-        const int spl_lim = persistent_spl_limit(c, adv ? 1 : 0);
+    // Per-bucket mappings and grid of fused-kernel class c; all_bpl runs
+    // every tile body-per-lane (in the system-per-lane class: one wave per
+    // SIMD with the full register file, partner loops unrolled).
+    auto set_class = [&](int c, bool all_bpl) -> hipError_t {
+        const int spl_lim = all_bpl ? 0 : persistent_spl_limit(c, adv ? 1 : 0);
         for (int i = n_large; i < nbk; ++i) {
             const int n = e->buckets[i].n;
             const int m = get_plan(n).mapping;
@@ -506,7 +516,8 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
             err = hipStreamSynchronize(e->stream);
         return err;
     };
-    FB_HIP(set_class(cls));   // also waits for the copies above (host vectors die at return)
+    FB_HIP(set_class(cls, false));   // also waits for the copies above (host vectors die at return)
+    bool tail_mode = false;
 
     ActiveLists AL[2];
     for (int k = 0; k < 2; ++k) {
@@ -591,7 +602,7 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                 break;
             continue;
         }
-        long long act = 0, spl_tiles = 0;
+        long long act = 0, spl_tiles = 0, bpl_waves = 0;
         if (compact) {
             // survivors of the second quantum sit in counts[0] (the small
             // buckets' entries; at most kMaxBodies - 1 of them)
@@ -606,8 +617,10 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                 break;
             }
             for (int i = 0; i < nb_small; ++i) {
-                act += e->h_pinned[8 + i];
-                spl_tiles += (e->h_pinned[8 + i] + 63) / 64;
+                const int c = e->h_pinned[8 + i], per = 64 / e->buckets[n_large + i].n;
+                act += c;
+                spl_tiles += (c + 63) / 64;
+                bpl_waves += (c + per - 1) / per;
             }
             if (n_large) {   // the large buckets keep no survivor lists
                 FB_HIP(launch_reset_counter(e->d_ints + 3, 1, e->stream));
@@ -627,18 +640,33 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
         }
         if (act == 0)
             break;
-        // The system-per-lane class runs one wavefront per SIMD; once the
-        // survivors' 64-system tiles no longer give every SIMD one, the body-
-        // per-lane class (a system over n lanes) keeps more of the device
-        // busy.  The two classes compute bitwise the same states, so the
-        // switch is invisible in the results.
-        if (compact && cls == 1 && p0.mapping == 0 && spl_tiles < 4LL * e->num_cu) {
-            hipError_t err = set_class(0);
-            if (err != hipSuccess) {
-                result = hip_fail(err, "class switch");
-                break;
+        // As survivors thin out (automatic class only): the system-per-lane
+        // class runs one wavefront per SIMD, so once the survivors' 64-system
+        // tiles no longer give every SIMD one, the body-per-lane class (a
+        // system over n lanes) keeps more of the device busy; once even its
+        // waves no longer give every SIMD one, each wave may as well have
+        // its SIMD's whole register file, and the full-register kernel runs
+        // the body-per-lane tiles with their partner loops unrolled (more
+        // independent work in flight per wave).  All these compute bitwise
+        // the same states, so the switches are invisible in the results.
+        if (compact && p0.mapping == 0 && !tail_mode) {
+            int to = -1;
+            bool all_bpl = false;
+            if (bpl_waves < (long long)FB_TAIL_WAVES_PER_SIMD * 4 * e->num_cu) {
+                to = 1;
+                all_bpl = true;
+            } else if (cls == 1 && spl_tiles < 4LL * e->num_cu) {
+                to = 0;
             }
-            result = capture();
+            if (to >= 0) {
+                hipError_t err = set_class(to, all_bpl);
+                if (err != hipSuccess) {
+                    result = hip_fail(err, "class switch");
+                    break;
+                }
+                tail_mode = all_bpl;
+                result = capture();
+            }
         }
     }
     release();

@@ -229,6 +229,35 @@ def test_persistent_equals_plain_bitwise(plans, cls):
         assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
 
 
+@pytest.mark.parametrize("n_sys", [65536, 3000])
+def test_adaptive_persistent_class_switches_are_bitwise_invisible(plans, n_sys):
+    """Adaptive steps with stop rules under compaction, automatic kernel
+    class: the run starts in the system-per-lane class (its tiles fill the
+    device) and moves to the body-per-lane class and then to unrolled
+    body-per-lane tiles in the full-register class as systems retire (the
+    smaller ensemble starts in the body-per-lane class and moves to the
+    unrolled tiles at the first check).  The states, step counts and
+    statuses equal the plain schedule's bitwise."""
+    fb = plans
+    for n in range(2, 17):
+        fb.set_plan(n, fb.MAP_AUTO, 2, 0)
+    fb.set_plan(0, fb.MAP_AUTO, 2, 8)
+    ens, p = gen.workload("lifetimes_65536x4-8", n_sys=n_sys)
+    t_end = 2 * math.pi * 3
+    base = dict(adaptive=True, eta=p["eta"], stop_rules=3, r_eject=p["r_eject"])
+    say("class switches vs plain", ens.n_sys)
+    out = []
+    for o in (fb.Opts(**base), fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=150, compact=True, **base)):
+        E = fb.from_gen(ens)
+        E.integrate(t_end, 0.0, o)
+        out.append(E.state())
+        E.close()
+    a, b = out
+    for k in ("pos", "vel", "t", "steps", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.sum(a["status"] == fb.ENCOUNTER) > n_sys // 50
+
+
 def test_time_reversal(fb):
     ens, p = gen.workload("parity_1024x3", n_sys=128)
     say("time reversal 128x3")
