@@ -126,14 +126,13 @@ __device__ __forceinline__ void correct_comp(const Coef &k, double bx, double bv
 
 // One wavefront's LDS slice: the current evaluation state of its 64 lanes
 // (as 16-byte pairs so a partner costs three ds_read_b128 and one b64),
-// the masses, and two reduction scratch rows.
+// the masses, and a reduction scratch row.
 struct BplLds {
     double2 xy[64];
     double2 zvx[64];
     double2 vyvz[64];
     double m[64];
     double red[64];
-    int redi[64];
 };
 
 // System-per-lane steps of at least this many bodies park the corrector
@@ -660,17 +659,26 @@ __device__ __forceinline__ int planet_partner(const int k, const int b)
     return k + 1 + (k + 1 >= b ? 1 : 0);
 }
 
-// One interaction of body i (this lane) with the partner stored at LDS index
-// idx: adds m_j A and m_j J (Eq. 1 and its time derivative).
-template <bool TS>
-__device__ __forceinline__ void bpl_interact(const BplLds &L, const int idx,
-                                             const double (&xi)[3], const double (&vi)[3],
-                                             double (&a)[3], double (&jk)[3], double &wmax)
+// A partner's evaluation state as read from the wavefront's LDS slice.
+struct Partner {
+    double2 p0, p1, p2;   // (x, y), (z, vx), (vy, vz)
+    double mj;
+};
+
+__device__ __forceinline__ Partner bpl_partner(const BplLds &L, const int idx)
 {
-    const double2 p0 = L.xy[idx];
-    const double2 p1 = L.zvx[idx];
-    const double2 p2 = L.vyvz[idx];
-    const double mj = L.m[idx];
+    return Partner{L.xy[idx], L.zvx[idx], L.vyvz[idx], L.m[idx]};
+}
+
+// One interaction of body i (this lane) with partner P: adds m_j A and m_j J
+// (Eq. 1 and its time derivative).
+template <bool TS>
+__device__ __forceinline__ void bpl_interact_p(const Partner &Pj, const double (&xi)[3],
+                                               const double (&vi)[3], double (&a)[3],
+                                               double (&jk)[3], double &wmax)
+{
+    const double2 p0 = Pj.p0, p1 = Pj.p1, p2 = Pj.p2;
+    const double mj = Pj.mj;
     const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
     const double ux = p1.y - vi[0], uy = p2.x - vi[1], uz = p2.y - vi[2];
     const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
@@ -689,6 +697,16 @@ __device__ __forceinline__ void bpl_interact(const BplLds &L, const int idx,
         const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
         wmax = fmax(wmax, fma(al, ru, u2) * ri2);
     }
+}
+
+// One interaction of body i (this lane) with the partner stored at LDS index
+// idx.
+template <bool TS>
+__device__ __forceinline__ void bpl_interact(const BplLds &L, const int idx,
+                                             const double (&xi)[3], const double (&vi)[3],
+                                             double (&a)[3], double (&jk)[3], double &wmax)
+{
+    bpl_interact_p<TS>(bpl_partner(L, idx), xi, vi, a, jk, wmax);
 }
 
 // Accelerations and jerks of this lane's body from all n-1 partners read
@@ -761,17 +779,24 @@ __device__ __forceinline__ double sys_sum(BplLds &L, int lane, int s, double v)
     return r;
 }
 
+// OR of the stop-flag bits (1, 2, 4) over the system's lanes (s, s + S, ...)
+// from three wave ballots: no LDS round trip.
 template <int N>
-__device__ __forceinline__ int sys_or(BplLds &L, int lane, int s, int v)
+__device__ __forceinline__ int sys_or_flags(int s, int v)
 {
     constexpr int S = 64 / N;
-    L.redi[lane] = v;
-    wave_sync();
-    int r = L.redi[s];
+    constexpr unsigned long long kBase = [] {
+        unsigned long long m = 0;
+        for (int k = 0; k < N; ++k)
+            m |= 1ull << (k * S);
+        return m;
+    }();
+    const unsigned long long sm = kBase << s;
+    int r = 0;
 #pragma unroll
-    for (int k = 1; k < N; ++k)
-        r |= L.redi[k * S + s];
-    wave_sync();
+    for (int bit = 1; bit <= 4; bit <<= 1)
+        if (__ballot((v & bit) != 0) & sm)
+            r |= bit;
     return r;
 }
 
@@ -817,7 +842,7 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
         }
     }
     wave_sync();
-    return sys_or<N>(L, lane, s, fl);
+    return sys_or_flags<N>(s, fl);
 }
 
 // Integrate one tile (floor(64/N) systems) with one body per lane for at
@@ -903,7 +928,7 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
         }
     }
     if (!ADV) {
-        const int fl = sys_or<N>(L, lane, s, (finite3(x) && finite3(v)) ? 0 : 1);
+        const int fl = sys_or_flags<N>(s, (finite3(x) && finite3(v)) ? 0 : 1);
         if (valid && fl)
             c.status = ST_NONFINITE;
     }
@@ -1996,7 +2021,7 @@ void k_plain_rkck(Bucket B, StepParams P, double eps)
         }
     }
     if (!ADV) {
-        const int fl = sys_or<N>(L, lane, s, (finite3(x) && finite3(v)) ? 0 : 1);
+        const int fl = sys_or_flags<N>(s, (finite3(x) && finite3(v)) ? 0 : 1);
         if (valid && fl)
             c.status = ST_NONFINITE;
     }
