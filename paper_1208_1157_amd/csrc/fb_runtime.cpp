@@ -644,7 +644,7 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
         // class runs one wavefront per SIMD, so once the survivors' 64-system
         // tiles no longer give every SIMD one, the body-per-lane class (a
         // system over n lanes) keeps more of the device busy; once even its
-        // waves no longer give every SIMD one, each wave may as well have
+        // waves no longer give every SIMD two, each wave may as well have
         // its SIMD's whole register file, and the full-register kernel runs
         // the body-per-lane tiles with their partner loops unrolled (more
         // independent work in flight per wave).  All these compute bitwise

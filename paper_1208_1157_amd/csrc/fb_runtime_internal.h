@@ -47,19 +47,23 @@ inline int plain_mapping(const Plan &p, const Bucket &B, bool adv, int num_cu)
 }
 
 // Fused persistent kernel class for a launch over buckets of these body
-// counts: the plan's choice, or (auto) the system-per-lane class when every
-// bucket can run system-per-lane in it and its tiles (64 systems each) give
-// every SIMD of the device a wavefront; that class runs one wavefront per
-// SIMD, so with fewer tiles the body-per-lane class, which spreads a system
-// over n lanes, keeps more of the device busy.
+// counts: the plan's choice, or (auto) for fixed steps the system-per-lane
+// class when every bucket can run system-per-lane in it and its tiles (64
+// systems each) give every SIMD of the device a wavefront; that class runs
+// one wavefront per SIMD, so with fewer tiles the body-per-lane class, which
+// spreads a system over n lanes, keeps more of the device busy.  With
+// adaptive steps or stop rules (auto) always the body-per-lane class: a
+// system-per-lane tile runs its 64 systems in lockstep, each to its own step
+// count, and measured 1.7x slower than body-per-lane tiles (about 10
+// systems each) on 65536 uneven-lifetime systems at full population.
 template <class BucketRange>
 int persistent_class(const Plan &p0, const BucketRange &buckets, bool adv, int num_cu)
 {
     if (p0.mapping == MAP_SPL)
         return 1;
-    if (p0.mapping == MAP_BPL)
+    if (p0.mapping == MAP_BPL || adv)
         return 0;
-    const int lim = persistent_spl_limit(1, adv ? 1 : 0);
+    const int lim = persistent_spl_limit(1, 0);
     long long tiles = 0;
     for (const Bucket &B : buckets) {
         if (B.n > lim)

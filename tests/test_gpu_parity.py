@@ -232,15 +232,14 @@ def test_persistent_equals_plain_bitwise(plans, cls):
 @pytest.mark.parametrize("n_sys", [65536, 3000])
 def test_adaptive_persistent_class_switches_are_bitwise_invisible(plans, n_sys):
     """Adaptive steps with stop rules under compaction, automatic kernel
-    class: the run starts in the system-per-lane class (its tiles fill the
-    device) and moves to the body-per-lane class and then to unrolled
-    body-per-lane tiles in the full-register class as systems retire (the
-    smaller ensemble starts in the body-per-lane class and moves to the
-    unrolled tiles at the first check).  The states, step counts and
-    statuses equal the plain schedule's bitwise."""
+    class: the run starts in the body-per-lane class and, once its waves no
+    longer give every SIMD two (at once for the smaller ensemble), moves to
+    unrolled body-per-lane tiles in the full-register class.  The states,
+    step counts and statuses equal bitwise those of the plain schedule run
+    system per lane (a third mapping of the same arithmetic)."""
     fb = plans
-    for n in range(2, 17):
-        fb.set_plan(n, fb.MAP_AUTO, 2, 0)
+    for n in range(2, 11):
+        fb.set_plan(n, fb.MAP_SPL, 2, 0)
     fb.set_plan(0, fb.MAP_AUTO, 2, 8)
     ens, p = gen.workload("lifetimes_65536x4-8", n_sys=n_sys)
     t_end = 2 * math.pi * 3
