@@ -69,16 +69,20 @@ def stop_margins(mass, pos, r_eject):
 
 def explain_adaptive_mismatch(ora, system, t_end, eta, stop_rules, r_eject, paper_rule,
                               rerun, got_status, got_steps, ref, margin=DECISION_MARGIN,
-                              tol=REL_TOL, max_steps=10**9):
+                              tol=REL_TOL, max_steps=10**9, start=None):
     """For one system whose final status or step count differs from the
     oracle's `ref`: rerun both sides up to the step before the first differing
     decision (rerun(k) returns the candidate's dict(pos, vel, t, status, steps)
     after at most k steps), require parity there, then require the criterion
     that flipped to lie within `margin` (relative) of its threshold in the
-    oracle's state.  Returns (k1, criterion, its margin); raises
-    AssertionError with the numbers otherwise."""
+    oracle's state.  With `start` (t0, acc, jerk, dt_next, steps of a run in
+    progress) both sides continue from that state and step counts are
+    absolute.  Returns (k1, criterion, its margin); raises AssertionError with
+    the numbers otherwise."""
     m, x0, v0 = system
-    kw = dict(t_end=t_end, eta=eta, stop_rules=stop_rules, r_eject=r_eject, paper_rule=paper_rule)
+    kw = dict(t_end=t_end, eta=eta, stop_rules=stop_rules, r_eject=r_eject, paper_rule=paper_rule,
+              **(start or {}))
+    s0 = int((start or {}).get("steps", 0))
     k1 = min(int(got_steps), int(ref["steps"]))
     assert k1 <= max_steps
     events = []
@@ -98,7 +102,7 @@ def explain_adaptive_mismatch(ora, system, t_end, eta, stop_rules, r_eject, pape
     if not crit:
         crit.add("clamp")            # one side took its shortened last step at k1
     pre = k1 - 1
-    if pre >= 1:
+    if pre >= max(1, s0 + 1):
         o_pre = ora.integrate_adaptive(m, x0, v0, max_steps=pre, **kw)
         g_pre = rerun(pre)
         assert o_pre["status"] == ora.MAXSTEPS and o_pre["steps"] == pre, o_pre["status"]
@@ -110,7 +114,7 @@ def explain_adaptive_mismatch(ora, system, t_end, eta, stop_rules, r_eject, pape
         assert ex <= tol and ev <= tol and et <= tol, (
             f"before the first differing decision (step {k1}): rel err x={ex:.3e} v={ev:.3e} t={et:.3e}")
     else:
-        o_pre = ora.integrate_adaptive(m, x0, v0, max_steps=0, **kw)
+        o_pre = ora.integrate_adaptive(m, x0, v0, max_steps=s0, **kw)
     o_k1 = ora.integrate_adaptive(m, x0, v0, max_steps=k1, **kw)
     hill, eject = stop_margins(m, o_k1["pos"], r_eject)
     margins = {
@@ -178,3 +182,65 @@ def check_adaptive_systems(fb, ora, ens, idx, st, t_end, eta, stop_rules, r_ejec
                                  f"{o['status']}/{o['steps']}; agree {agree}, flips {len(flips)}): {exc}")
         flips.append((s, k1, crit, margin))
     return agree, len(flips), worst, flips
+
+
+def explain_rkck_mismatch(ora, system, t_end, eps, dt0, rerun, got_steps, ref, margin=DECISION_MARGIN,
+                          tol=REL_TOL):
+    """Adaptive Runge-Kutta Cash-Karp: for one system whose accepted-step
+    count differs from the oracle's, find the first accepted step k* after
+    which the two sides' times differ (bisection over max_steps; a trial
+    accepted on one side and rejected on the other, or a last step clamped on
+    one side only, shows in t at once), require parity of the state and time
+    after k* - 1 steps, then require that one of step k*'s decisions in the
+    oracle's state -- the acceptance of each trial (error norm E against 1) or
+    the clamp onto t_end -- lies within `margin` of its threshold.  rerun(k)
+    returns the candidate's dict(pos, vel, t, steps) after at most k accepted
+    steps.  Returns (k*, criterion, margin)."""
+    m, x0, v0 = system
+    k1 = min(int(got_steps), int(ref["steps"]))
+
+    def ora_at(k):
+        return ora.integrate_rkck_adaptive(m, x0, v0, t_end, eps, dt0, max_steps=k)
+
+    def same_t(k):
+        a, b = rerun(k), ora_at(k)
+        return abs(float(a["t"]) - b["t"]) <= 1e-12 * max(abs(b["t"]), 1e-300)
+
+    if same_t(k1):
+        # identical through step k1: the side that stopped there clamped its
+        # step k1 onto t_end and the other did not
+        kstar = k1
+    else:
+        lo, hi = 0, k1              # same t after lo steps, different after hi
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if same_t(mid):
+                lo = mid
+            else:
+                hi = mid
+        kstar = hi
+    a, b = rerun(kstar - 1), ora_at(kstar - 1)
+    n = [len(m)]
+    ex = per_system_rel_err(n, a["pos"], b["pos"])[0]
+    ev = per_system_rel_err(n, a["vel"], b["vel"])[0]
+    assert ex <= tol and ev <= tol, (
+        f"before the first differing decision (step {kstar}): rel err x={ex:.3e} v={ev:.3e}")
+    # step k*'s decisions in the oracle's state: its trials, then the clamp
+    t, h = b["t"], b["dt_next"]
+    margins = {}
+    x, v = b["pos"], b["vel"]
+    margins["clamp"] = float("inf")
+    for trial in range(64):
+        last = t + h >= t_end
+        margins["clamp"] = min(margins["clamp"], abs(t + h - t_end) / abs(t_end))
+        hh = t_end - t if last else h
+        _, _, exr, evr = ora.rkck_step(m, x, v, hh)
+        E = ora.rkck_error_norm(x, v, exr, evr, eps)
+        margins[f"accept trial {trial}"] = abs(E - 1.0)
+        if E <= 1.0:
+            break
+        h = hh * max(0.1, 0.9 * E ** -0.25)
+    crit = min(margins, key=margins.get)
+    assert margins[crit] <= margin, (
+        f"step {kstar} differs but no decision sits within {margin:g} of its threshold: {margins}")
+    return kstar, crit, margins[crit]
