@@ -802,8 +802,9 @@ __device__ __forceinline__ int sys_or_flags(int s, int v)
 
 template <int N, bool ILP = false>
 __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const int b,
-                                              const int s, const double mi, const double (&x)[3],
-                                              const double (&v)[3], const StepParams &P)
+                                              const int s, const double mi, const double inv24m0,
+                                              const double (&x)[3], const double (&v)[3],
+                                              const StepParams &P)
 {
     constexpr int S = 64 / N;
     int fl = (finite3(x) && finite3(v)) ? 0 : 1;
@@ -820,7 +821,6 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
         if ((P.stop_rules & 2) && rb > P.r_eject)
             fl |= 4;
         if (P.stop_rules & 1) {
-            const double inv24m0 = 1.0 / (24.0 * L.m[s]);
             auto hill = [&](const int k) {
                 const int idx = planet_partner(k, b) * S + s;
                 const double2 q0 = L.xy[idx];
@@ -883,6 +883,8 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
     }
     L.m[lane] = mi;
     wave_sync();
+    // Hill-test scale of the system's star, fixed over the run.
+    const double inv24m0 = ADV ? 1.0 / (24.0 * L.m[s]) : 0.0;
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
         bool last = false;
@@ -922,7 +924,7 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
             finish_step(c, P, last, h, dtp);
         }
         if (ADV) {
-            const int fl = bpl_stop_flags<N, WIDE>(L, lane, b, s, mi, x, v, P);
+            const int fl = bpl_stop_flags<N, WIDE>(L, lane, b, s, mi, inv24m0, x, v, P);
             if (act && fl)
                 c.status = status_of_flags(fl);
         }
@@ -995,16 +997,21 @@ __device__ __forceinline__ void append_survivors(const ActiveLists &AL, int bk, 
         AL.next[AL.base[bk] + base + pre] = slot;
 }
 
+// The tile functions are separately compiled, so their reference arguments
+// arrive as generic pointers; the step loop works on a register copy of the
+// step parameters (read once), not on memory it would reload after every LDS
+// exchange.
 template <int N, bool ADV>
 __device__ __noinline__ bool spl_tile(const Bucket &B, const Tile &T, const int *list,
                                       const StepParams &P, int &slot)
 {
+    const StepParams Pr = P;
     const int lane = threadIdx.x & 63;
     slot = 0;
     if (lane >= T.count)
         return false;
     slot = list ? list[T.first + lane] : T.first + lane;
-    spl_run<N, ADV, true>(B, slot, P);
+    spl_run<N, ADV, true>(B, slot, Pr);
     return B.status[slot] == ST_ACTIVE;
 }
 
@@ -1014,7 +1021,8 @@ template <int N, bool ADV, bool CLS>
 __device__ __noinline__ bool bpl_tile(const Bucket &B, const Tile &T, const int *list,
                                       const StepParams &P, int &slot)
 {
-    return bpl_run<N, ADV, CLS>(B, T.first, T.count, list, P, slot);
+    const StepParams Pr = P;
+    return bpl_run<N, ADV, CLS>(B, T.first, T.count, list, Pr, slot);
 }
 
 // Tile dispatch.  The body-per-lane class (SPLC false) keeps the fused
@@ -1954,6 +1962,8 @@ void k_plain_rkck(Bucket B, StepParams P, double eps)
     }
     L.m[lane] = mi;
     wave_sync();
+    // Hill-test scale of the system's star, fixed over the run.
+    const double inv24m0 = ADV ? 1.0 / (24.0 * L.m[s]) : 0.0;
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
         bool last = false;
