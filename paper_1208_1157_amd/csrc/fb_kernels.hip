@@ -845,6 +845,96 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
     return sys_or_flags<N>(s, fl);
 }
 
+// Full-register-file variants of the evaluation and of the stop-rule pass,
+// for a wave that has its SIMD to itself and so waits out every LDS round
+// trip and every dependent latency: the partner slots (pidx) and masses (pm)
+// of this lane's body, in evaluation order, are fixed over the run and held
+// in registers; all partner reads are issued before the first interaction.
+template <int N>
+__device__ __forceinline__ int eval_partner(const int k, const int b)
+{
+    const int skip = b == 0 ? (1 << 20) : b;
+    return k < N - 2 ? k + 1 + (k + 1 >= skip ? 1 : 0) : (b == 0 ? N - 1 : 0);
+}
+
+template <int N, bool TS>
+__device__ __forceinline__ void bpl_eval_regs(BplLds &L, const int lane, const int (&pidx)[N - 1],
+                                              const double (&pm)[N - 1], const double (&xi)[3],
+                                              const double (&vi)[3], double (&a)[3],
+                                              double (&jk)[3], double &wmax)
+{
+    L.xy[lane] = make_double2(xi[0], xi[1]);
+    L.zvx[lane] = make_double2(xi[2], vi[0]);
+    L.vyvz[lane] = make_double2(vi[1], vi[2]);
+    wave_sync();
+    Partner pj[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k)
+        pj[k] = Partner{L.xy[pidx[k]], L.zvx[pidx[k]], L.vyvz[pidx[k]], pm[k]};
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a[c] = 0.0;
+        jk[c] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k)
+        bpl_interact_p<TS>(pj[k], xi, vi, a, jk, wmax);
+    wave_sync();
+}
+
+// Stop-rule flags (as bpl_stop_flags) and the system maximum of the step
+// rule's w (as sys_max) from one exchange: each lane publishes its position
+// and w, and forms its partners' astrocentric distances itself (the same
+// operations on the same values as the partners' own, so the same bits).
+template <int N>
+__device__ __forceinline__ int bpl_stop_flags_regs(BplLds &L, const int lane, const int b,
+                                                   const int s, const int (&pidx)[N - 1],
+                                                   const double (&pm)[N - 1], const double mi,
+                                                   const double inv24m0, const double (&x)[3],
+                                                   const double (&v)[3], const double w,
+                                                   double &wsys, const StepParams &P)
+{
+    int fl = (finite3(x) && finite3(v)) ? 0 : 1;
+    L.xy[lane] = make_double2(x[0], x[1]);
+    L.zvx[lane] = make_double2(x[2], w);
+    wave_sync();
+    double2 q0[N - 1], q1[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        q0[k] = L.xy[pidx[k]];
+        q1[k] = L.zvx[pidx[k]];
+    }
+    const double2 s0 = L.xy[s];
+    const double2 s1 = L.zvx[s];
+    wave_sync();
+    // max is exact, so the partners' order gives the body-order result
+    wsys = w;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k)
+        wsys = fmax(wsys, q1[k].y);
+    auto radius = [&](const double px, const double py, const double pz) {
+        const double dx = px - s0.x, dy = py - s0.y, dz = pz - s1.x;
+        return sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    };
+    const double rb = radius(x[0], x[1], x[2]);
+    if (b >= 1) {
+        if ((P.stop_rules & 2) && rb > P.r_eject)
+            fl |= 4;
+        if (P.stop_rules & 1) {
+#pragma unroll
+            for (int k = 0; k < N - 2; ++k) {
+                const double ex = x[0] - q0[k].x, ey = x[1] - q0[k].y, ez = x[2] - q1[k].x;
+                const double sep2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                const double rj = radius(q0[k].x, q0[k].y, q1[k].x);
+                if (hill_close(sep2, mi, pm[k], inv24m0, rb, rj))
+                    fl |= 2;
+            }
+        }
+    }
+    return sys_or_flags<N>(s, fl);
+}
+
 // Integrate one tile (floor(64/N) systems) with one body per lane for at
 // most P.quantum steps.  Every lane of the wavefront executes the same
 // control flow (the LDS exchanges need it); lanes of finished, padding or
@@ -885,6 +975,15 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
     wave_sync();
     // Hill-test scale of the system's star, fixed over the run.
     const double inv24m0 = ADV ? 1.0 / (24.0 * L.m[s]) : 0.0;
+    // The full-register-file class keeps the partner tables in registers.
+    constexpr bool REGS = WIDE && N <= 8;
+    int pidx[N - 1];
+    double pm[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        pidx[k] = REGS ? eval_partner<N>(k, b) * S + s : 0;
+        pm[k] = REGS ? L.m[pidx[k]] : 0.0;
+    }
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
         bool last = false;
@@ -897,14 +996,50 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
         for (int cc = 0; cc < 3; ++cc)
             predict_comp(k, x[cc], v[cc], a0[cc], j0[cc], xc[cc], vc[cc], bx[cc], bv[cc]);
         double w = 0.0;
-        bpl_eval<N, false, WIDE>(L, lane, b, s, xc, vc, ak, jk, w);
+        if constexpr (REGS)
+            bpl_eval_regs<N, false>(L, lane, pidx, pm, xc, vc, ak, jk, w);
+        else
+            bpl_eval<N, false, WIDE>(L, lane, b, s, xc, vc, ak, jk, w);
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
             correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
-        bpl_eval<N, ADV, WIDE>(L, lane, b, s, xc, vc, ak, jk, w);
+        if constexpr (REGS)
+            bpl_eval_regs<N, ADV>(L, lane, pidx, pm, xc, vc, ak, jk, w);
+        else
+            bpl_eval<N, ADV, WIDE>(L, lane, b, s, xc, vc, ak, jk, w);
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
             correct_comp(k, bx[cc], bv[cc], ak[cc], jk[cc], xc[cc], vc[cc]);
+        if constexpr (ADV && REGS) {
+            // commit, then one exchange for the step rule's maximum and the
+            // stop rules (same values and order of decisions as below)
+            double dtp = 0.0;
+            if (P.adaptive == 2) {
+                const double aa = fma(ak[2], ak[2], fma(ak[1], ak[1], ak[0] * ak[0]));
+                const double jj = fma(jk[2], jk[2], fma(jk[1], jk[1], jk[0] * jk[0]));
+                dtp = P.eta * rsqrt_nr(sys_sum<N>(L, lane, s, jj / aa));
+            }
+            if (act) {
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    x[cc] = xc[cc];
+                    v[cc] = vc[cc];
+                    a0[cc] = ak[cc];
+                    j0[cc] = jk[cc];
+                }
+            }
+            double wsys = 0.0;
+            const int fl = bpl_stop_flags_regs<N>(L, lane, b, s, pidx, pm, mi, inv24m0, x, v, w,
+                                                  wsys, P);
+            if (P.adaptive == 1)
+                dtp = P.eta * rsqrt_nr(wsys);
+            if (act) {
+                finish_step(c, P, last, h, dtp);
+                if (fl)
+                    c.status = status_of_flags(fl);
+            }
+            continue;
+        }
         double dtp = 0.0;
         if (ADV && P.adaptive == 1)
             dtp = P.eta * rsqrt_nr(sys_max<N>(L, lane, s, w));
@@ -1962,8 +2097,6 @@ void k_plain_rkck(Bucket B, StepParams P, double eps)
     }
     L.m[lane] = mi;
     wave_sync();
-    // Hill-test scale of the system's star, fixed over the run.
-    const double inv24m0 = ADV ? 1.0 / (24.0 * L.m[s]) : 0.0;
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
         bool last = false;
