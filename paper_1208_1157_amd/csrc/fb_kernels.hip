@@ -125,14 +125,14 @@ __device__ __forceinline__ void correct_comp(const Coef &k, double bx, double bv
 }
 
 // One wavefront's LDS slice: the current evaluation state of its 64 lanes
-// (as 16-byte pairs so a partner costs three ds_read_b128 and one b64),
-// the masses, and a reduction scratch row.
+// (as 16-byte pairs so a partner costs three ds_read_b128 and one b64), and
+// per lane its mass beside a reduction scratch value, so every row of a
+// partner sits at the same 16-byte slot offset.
 struct BplLds {
     double2 xy[64];
     double2 zvx[64];
     double2 vyvz[64];
-    double m[64];
-    double red[64];
+    double2 mr[64];   // (mass, reduction scratch)
 };
 
 // System-per-lane steps of at least this many bodies park the corrector
@@ -653,10 +653,17 @@ __device__ __forceinline__ void spl_run(const Bucket &B, const int slot, const S
 // ---------------------------------------------------------------------------
 
 
-// k-th planet partner of planet b (0 <= k < n-2).
-__device__ __forceinline__ int planet_partner(const int k, const int b)
+// LDS slot of the k-th planet partner (0 <= k < N-2, the other planets in
+// ascending order) of body b of system s, with own = b S (the star lane
+// passes 64, past every body): (k + 1) S + s, moved one body up from b on.
+// The body offset (k + 1) S is uniform, so the slot costs a compare, a select
+// and an add per partner.
+template <int N>
+__device__ __forceinline__ int partner_slot(const int k, const int s, const int own)
 {
-    return k + 1 + (k + 1 >= b ? 1 : 0);
+    constexpr int S = 64 / N;
+    const int ks = (k + 1) * S;
+    return s + ks + (ks >= own ? S : 0);
 }
 
 // A partner's evaluation state as read from the wavefront's LDS slice.
@@ -667,7 +674,7 @@ struct Partner {
 
 __device__ __forceinline__ Partner bpl_partner(const BplLds &L, const int idx)
 {
-    return Partner{L.xy[idx], L.zvx[idx], L.vyvz[idx], L.m[idx]};
+    return Partner{L.xy[idx], L.zvx[idx], L.vyvz[idx], L.mr[idx].x};
 }
 
 // One interaction of body i (this lane) with partner P: adds m_j A and m_j J
@@ -732,19 +739,15 @@ __device__ __forceinline__ void bpl_eval(BplLds &L, const int lane, const int b,
         a[c] = 0.0;
         jk[c] = 0.0;
     }
-    const int skip = b == 0 ? (1 << 20) : b;
+    const int own = b == 0 ? 64 : b * S;
     if constexpr (ILP) {
 #pragma unroll
-        for (int k = 0; k < N - 2; ++k) {
-            const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
-            bpl_interact<TS>(L, j * S + s, xi, vi, a, jk, wmax);
-        }
+        for (int k = 0; k < N - 2; ++k)
+            bpl_interact<TS>(L, partner_slot<N>(k, s, own), xi, vi, a, jk, wmax);
     } else {
 #pragma unroll FB_BPL_UNROLL
-        for (int k = 0; k < N - 2; ++k) {
-            const int j = k + 1 + (k + 1 >= skip ? 1 : 0);
-            bpl_interact<TS>(L, j * S + s, xi, vi, a, jk, wmax);
-        }
+        for (int k = 0; k < N - 2; ++k)
+            bpl_interact<TS>(L, partner_slot<N>(k, s, own), xi, vi, a, jk, wmax);
     }
     bpl_interact<TS>(L, (b == 0 ? N - 1 : 0) * S + s, xi, vi, a, jk, wmax);
     wave_sync();
@@ -754,12 +757,12 @@ template <int N>
 __device__ __forceinline__ double sys_max(BplLds &L, int lane, int s, double v)
 {
     constexpr int S = 64 / N;
-    L.red[lane] = v;
+    L.mr[lane].y = v;
     wave_sync();
-    double r = L.red[s];
+    double r = L.mr[s].y;
 #pragma unroll
     for (int k = 1; k < N; ++k)
-        r = fmax(r, L.red[k * S + s]);
+        r = fmax(r, L.mr[k * S + s].y);
     wave_sync();
     return r;
 }
@@ -769,12 +772,12 @@ template <int N>
 __device__ __forceinline__ double sys_sum(BplLds &L, int lane, int s, double v)
 {
     constexpr int S = 64 / N;
-    L.red[lane] = v;
+    L.mr[lane].y = v;
     wave_sync();
-    double r = L.red[s];
+    double r = L.mr[s].y;
 #pragma unroll
     for (int k = 1; k < N; ++k)
-        r += L.red[k * S + s];
+        r += L.mr[k * S + s].y;
     wave_sync();
     return r;
 }
@@ -815,19 +818,20 @@ __device__ __forceinline__ int bpl_stop_flags(BplLds &L, const int lane, const i
     const double2 s1 = L.zvx[s];
     const double dx = x[0] - s0.x, dy = x[1] - s0.y, dz = x[2] - s1.x;
     const double rb = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-    L.red[lane] = rb;
+    L.mr[lane].y = rb;
     wave_sync();
     if (b >= 1) {
         if ((P.stop_rules & 2) && rb > P.r_eject)
             fl |= 4;
         if (P.stop_rules & 1) {
+            const int own = b * S;
             auto hill = [&](const int k) {
-                const int idx = planet_partner(k, b) * S + s;
+                const int idx = partner_slot<N>(k, s, own);
                 const double2 q0 = L.xy[idx];
                 const double2 q1 = L.zvx[idx];
                 const double ex = x[0] - q0.x, ey = x[1] - q0.y, ez = x[2] - q1.x;
                 const double sep2 = fma(ez, ez, fma(ey, ey, ex * ex));
-                if (hill_close(sep2, mi, L.m[idx], inv24m0, rb, L.red[idx]))
+                if (hill_close(sep2, mi, L.mr[idx].x, inv24m0, rb, L.mr[idx].y))
                     fl |= 2;
             };
             if constexpr (ILP) {
@@ -971,10 +975,10 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
         }
         c = load_clock(B, slot);
     }
-    L.m[lane] = mi;
+    L.mr[lane].x = mi;
     wave_sync();
     // Hill-test scale of the system's star, fixed over the run.
-    const double inv24m0 = ADV ? 1.0 / (24.0 * L.m[s]) : 0.0;
+    const double inv24m0 = ADV ? 1.0 / (24.0 * L.mr[s].x) : 0.0;
     // The full-register-file class keeps the partner tables in registers.
     constexpr bool REGS = WIDE && N <= 8;
     int pidx[N - 1];
@@ -982,7 +986,7 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
         pidx[k] = REGS ? eval_partner<N>(k, b) * S + s : 0;
-        pm[k] = REGS ? L.m[pidx[k]] : 0.0;
+        pm[k] = REGS ? L.mr[pidx[k]].x : 0.0;
     }
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
@@ -2043,7 +2047,7 @@ __device__ __forceinline__ void rk_accel(BplLds &L, const int lane, const int b,
         const double2 p1 = L.zvx[idx];
         const double rx = p0.x - xi[0], ry = p0.y - xi[1], rz = p1.x - xi[2];
         const double ri = rsqrt_nr(fma(rz, rz, fma(ry, ry, rx * rx)));
-        const double mr3 = L.m[idx] * (ri * ri * ri);
+        const double mr3 = L.mr[idx].x * (ri * ri * ri);
         acc[0] = fma(mr3, rx, acc[0]);
         acc[1] = fma(mr3, ry, acc[1]);
         acc[2] = fma(mr3, rz, acc[2]);
@@ -2095,7 +2099,7 @@ void k_plain_rkck(Bucket B, StepParams P, double eps)
         }
         c = load_clock(B, slot);
     }
-    L.m[lane] = mi;
+    L.mr[lane].x = mi;
     wave_sync();
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
