@@ -1215,11 +1215,23 @@ __device__ __forceinline__ void persistent_body(const Bucket *__restrict__ bucke
 {
     const int ntiles = *ntiles_p;
     const int lane = threadIdx.x & 63;
+    // Each wave's first tile is its own index; the rest come from the queue
+    // (past the first round).  Workgroups are dispatched across the CUs in
+    // index order, so when the tiles are fewer than the resident waves (the
+    // population has thinned) they land one per SIMD rather than wherever
+    // the queue's atomics happen to be served first.
+    const int nwaves = (int)(gridDim.x * (blockDim.x >> 6));
+    int first = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     for (;;) {
         int t = 0;
-        if (lane == 0)
-            t = atomicAdd(head, 1);
-        t = __builtin_amdgcn_readfirstlane(t);
+        if (first >= 0) {
+            t = first;
+            first = -1;
+        } else {
+            if (lane == 0)
+                t = nwaves + atomicAdd(head, 1);
+            t = __builtin_amdgcn_readfirstlane(t);
+        }
         if (t >= ntiles)
             break;
         const Tile T = tiles[t];
