@@ -288,6 +288,40 @@ __device__ __forceinline__ int status_of_flags(int fl)
     return (fl & 1) ? ST_NONFINITE : (fl & 2) ? ST_ENCOUNTER : (fl & 4) ? ST_EJECTED : ST_ACTIVE;
 }
 
+// Adaptive-step forms of plan_step and finish_step (the same tests in the
+// same order) as selects rather than branches, for a wave that runs alone on
+// its SIMD, where every branch and exec-mask change is latency on the step's
+// critical path.  A lane whose system is not active keeps its clock.
+__device__ __forceinline__ bool plan_step_adaptive(Clock &c, const StepParams &P, double &h,
+                                                   bool &last)
+{
+    const bool running = c.status == ST_ACTIVE;
+    // every test evaluated, then the first that holds wins
+    const bool done = !(c.t < c.t_end);
+    const bool maxed = c.steps >= P.max_steps;
+    const bool nonfinite = __builtin_isnan(c.dtn);
+    const bool stalled = !(c.dtn >= 1e-12 * fabs(c.t_end));
+    int ns = stalled ? ST_STALLED : ST_ACTIVE;
+    ns = nonfinite ? ST_NONFINITE : ns;
+    ns = maxed ? ST_MAXSTEPS : ns;
+    ns = done ? ST_DONE : ns;
+    c.status = running ? ns : c.status;
+    last = c.t + c.dtn >= c.t_end;
+    h = last ? c.t_end - c.t : c.dtn;
+    return running && ns == ST_ACTIVE;
+}
+
+__device__ __forceinline__ void finish_step_adaptive(Clock &c, const bool act, const bool last,
+                                                     const double h, const double dt_prop,
+                                                     const int fl)
+{
+    c.steps += act ? 1 : 0;
+    c.t = act ? (last ? c.t_end : c.t + h) : c.t;
+    c.dtn = act ? dt_prop : c.dtn;
+    const int st = fl ? status_of_flags(fl) : (last ? ST_DONE : c.status);
+    c.status = act ? st : c.status;
+}
+
 // ---------------------------------------------------------------------------
 // system-per-lane (SPL)
 // ---------------------------------------------------------------------------
@@ -962,7 +996,7 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
     const size_t pitch = B.pitch;
     double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
     double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
-    Clock c;
+    Clock c{};
     c.status = ST_DONE;
     if (valid) {
         mi = B.st[(R_M * N + b) * pitch + slot];
@@ -991,7 +1025,11 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
     for (int q = 0; q < P.quantum; ++q) {
         double h = 0.0;
         bool last = false;
-        const bool act = valid && plan_step(c, P, h, last);
+        bool act;
+        if constexpr (ADV && REGS)   // invalid lanes hold an inactive clock
+            act = P.adaptive ? plan_step_adaptive(c, P, h, last) : valid && plan_step(c, P, h, last);
+        else
+            act = valid && plan_step(c, P, h, last);
         if (!__any(act))
             break;
         const Coef k = make_coef(h);
@@ -1037,7 +1075,9 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
                                                   wsys, P);
             if (P.adaptive == 1)
                 dtp = P.eta * rsqrt_nr(wsys);
-            if (act) {
+            if (P.adaptive) {
+                finish_step_adaptive(c, act, last, h, dtp, fl);
+            } else if (act) {
                 finish_step(c, P, last, h, dtp);
                 if (fl)
                     c.status = status_of_flags(fl);
@@ -1139,12 +1179,43 @@ __device__ __forceinline__ void append_survivors(const ActiveLists &AL, int bk, 
 // The tile functions are separately compiled, so their reference arguments
 // arrive as generic pointers; the step loop works on a register copy of the
 // step parameters (read once), not on memory it would reload after every LDS
-// exchange.
+// exchange.  The copy is made wave-uniform (scalar registers), so the tests
+// on it are scalar branches rather than exec-mask changes.
+__device__ __forceinline__ int uniform_i(const int v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ long long uniform_ll(const long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double uniform_d(const double v)
+{
+    return __longlong_as_double(uniform_ll(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ StepParams uniform_params(const StepParams &P)
+{
+    StepParams u;
+    u.adaptive = uniform_i(P.adaptive);
+    u.stop_rules = uniform_i(P.stop_rules);
+    u.eta = uniform_d(P.eta);
+    u.r_eject = uniform_d(P.r_eject);
+    u.max_steps = uniform_ll(P.max_steps);
+    u.quantum = uniform_i(P.quantum);
+    u.pad = 0;
+    return u;
+}
+
 template <int N, bool ADV>
 __device__ __noinline__ bool spl_tile(const Bucket &B, const Tile &T, const int *list,
                                       const StepParams &P, int &slot)
 {
-    const StepParams Pr = P;
+    const StepParams Pr = uniform_params(P);
     const int lane = threadIdx.x & 63;
     slot = 0;
     if (lane >= T.count)
@@ -1160,7 +1231,7 @@ template <int N, bool ADV, bool CLS>
 __device__ __noinline__ bool bpl_tile(const Bucket &B, const Tile &T, const int *list,
                                       const StepParams &P, int &slot)
 {
-    const StepParams Pr = P;
+    const StepParams Pr = uniform_params(P);
     return bpl_run<N, ADV, CLS>(B, T.first, T.count, list, Pr, slot);
 }
 
