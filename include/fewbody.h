@@ -116,7 +116,10 @@ typedef struct {
     int64_t max_steps;          /* per-system cap on steps (<=0: unlimited)     */
     int32_t schedule;           /* FB_SCHED_*                                   */
     int32_t steps_per_quantum;  /* persistent schedule: steps per launch
-                                   (<=0: whole run in one launch)               */
+                                   (<=0: whole run in one launch); with
+                                   compact and the automatic fused class,
+                                   64x this once every surviving tile has a
+                                   wavefront of its own                         */
     int32_t compact;            /* persistent schedule: rebuild tiles from the
                                    still-active systems after every quantum     */
 } fb_opts;
