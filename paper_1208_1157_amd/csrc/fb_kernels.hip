@@ -80,6 +80,38 @@ __device__ __forceinline__ bool finite3(const double (&p)[3])
     return __builtin_isfinite(p[0]) && __builtin_isfinite(p[1]) && __builtin_isfinite(p[2]);
 }
 
+// Wave-uniform copies (scalar registers) of values every lane holds alike:
+// tests on them are scalar branches rather than exec-mask changes.
+__device__ __forceinline__ int uniform_i(const int v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ long long uniform_ll(const long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double uniform_d(const double v)
+{
+    return __longlong_as_double(uniform_ll(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ StepParams uniform_params(const StepParams &P)
+{
+    StepParams u;
+    u.adaptive = uniform_i(P.adaptive);
+    u.stop_rules = uniform_i(P.stop_rules);
+    u.eta = uniform_d(P.eta);
+    u.r_eject = uniform_d(P.r_eject);
+    u.max_steps = uniform_ll(P.max_steps);
+    u.quantum = uniform_i(P.quantum);
+    u.pad = 0;
+    return u;
+}
+
 // Step coefficients of the predictor (Eq. 3) and corrector (Eq. 4).
 struct Coef {
     double h, hh2, hhh6;       // predictor: h, h^2/2, h^3/6
@@ -1130,11 +1162,24 @@ __device__ __forceinline__ bool bpl_run(const Bucket &B, const int first, const 
 // ---------------------------------------------------------------------------
 // kernels: plain schedule (one launch per homogeneous bucket)
 // ---------------------------------------------------------------------------
+// The system-per-lane run of 9 and 10 bodies as a separately compiled
+// function: inlined into the kernel, the register allocator spilled 92 and
+// 476 bytes per lane to scratch memory; as a callee it spills to AGPRs only.
+template <int N, bool ADV>
+__device__ __noinline__ void spl_plain_call(const Bucket &B, const int slot, const StepParams &P)
+{
+    spl_run<N, ADV, false>(B, slot, uniform_params(P));
+}
+
 template <int N, bool ADV>
 __global__ __launch_bounds__(256) void k_plain_spl(Bucket B, StepParams P)
 {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot < B.count)
+    if (slot >= B.count)
+        return;
+    if constexpr (N >= 9)
+        spl_plain_call<N, ADV>(B, slot, P);
+    else
         spl_run<N, ADV, false>(B, slot, P);
 }
 
@@ -1181,36 +1226,6 @@ __device__ __forceinline__ void append_survivors(const ActiveLists &AL, int bk, 
 // step parameters (read once), not on memory it would reload after every LDS
 // exchange.  The copy is made wave-uniform (scalar registers), so the tests
 // on it are scalar branches rather than exec-mask changes.
-__device__ __forceinline__ int uniform_i(const int v)
-{
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ long long uniform_ll(const long long v)
-{
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
-    return (long long)(((unsigned long long)hi << 32) | lo);
-}
-
-__device__ __forceinline__ double uniform_d(const double v)
-{
-    return __longlong_as_double(uniform_ll(__double_as_longlong(v)));
-}
-
-__device__ __forceinline__ StepParams uniform_params(const StepParams &P)
-{
-    StepParams u;
-    u.adaptive = uniform_i(P.adaptive);
-    u.stop_rules = uniform_i(P.stop_rules);
-    u.eta = uniform_d(P.eta);
-    u.r_eject = uniform_d(P.r_eject);
-    u.max_steps = uniform_ll(P.max_steps);
-    u.quantum = uniform_i(P.quantum);
-    u.pad = 0;
-    return u;
-}
-
 template <int N, bool ADV>
 __device__ __noinline__ bool spl_tile(const Bucket &B, const Tile &T, const int *list,
                                       const StepParams &P, int &slot)
