@@ -234,9 +234,11 @@ def test_adaptive_persistent_class_switches_are_bitwise_invisible(plans, n_sys):
     """Adaptive steps with stop rules under compaction, automatic kernel
     class: the run starts in the body-per-lane class and, once its waves no
     longer give every SIMD two (at once for the smaller ensemble), moves to
-    unrolled body-per-lane tiles in the full-register class.  The states,
-    step counts and statuses equal bitwise those of the plain schedule run
-    system per lane (a third mapping of the same arithmetic)."""
+    unrolled body-per-lane tiles in the full-register class, and, once those
+    tiles no longer outnumber the kernel's waves (also at once for the
+    smaller ensemble), to 64-fold quanta.  The states, step counts and
+    statuses equal bitwise those of the plain schedule run system per lane
+    (a third mapping of the same arithmetic)."""
     fb = plans
     for n in range(2, 11):
         fb.set_plan(n, fb.MAP_SPL, 2, 0)
