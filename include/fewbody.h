@@ -522,6 +522,11 @@ fb_status fb_server_result(fb_server *s, int64_t req_id, double *pos, double *ve
 /* Cancel a queued or running request (it settles as CANCELLED). */
 fb_status fb_server_cancel(fb_server *s, int64_t req_id);
 
+/* Forget a settled (DONE, CANCELLED or FAILED) request without reading its
+ * results, freeing what the server still holds for it; a later call on it
+ * returns FB_E_NOTFOUND.  FB_E_STATE while it is queued or running. */
+fb_status fb_server_release(fb_server *s, int64_t req_id);
+
 fb_status fb_server_get_stats(fb_server *s, fb_server_stats *out);
 
 /* Stop the worker (resident work is abandoned) and free the server. */

@@ -1133,6 +1133,26 @@ fb_status fb_server_cancel(fb_server *S, int64_t req_id)
     return FB_OK;
 }
 
+fb_status fb_server_release(fb_server *S, int64_t req_id)
+{
+    if (!S)
+        return fail(FB_E_INVAL, "server is NULL");
+    std::unique_ptr<Request> R;   // freed after the lock is released
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->all.find(req_id);
+        if (it == S->all.end())
+            return fail(FB_E_NOTFOUND, "unknown request %lld", (long long)req_id);
+        // settled requests are in no worker list any more
+        if (it->second->state < FB_REQ_DONE)
+            return fail(FB_E_STATE, "request %lld is not settled (state %d)", (long long)req_id,
+                        it->second->state);
+        R = std::move(it->second);
+        S->all.erase(it);
+    }
+    return FB_OK;
+}
+
 fb_status fb_server_get_stats(fb_server *S, fb_server_stats *out)
 {
     if (!S || !out)

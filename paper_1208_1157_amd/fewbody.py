@@ -122,6 +122,7 @@ _SIGS = {
     "fb_server_wait": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(_i32)]),
     "fb_server_result": (ctypes.c_int, [_p, _i64, _p, _p, _p, _p, _p, _p]),
     "fb_server_cancel": (ctypes.c_int, [_p, _i64]),
+    "fb_server_release": (ctypes.c_int, [_p, _i64]),
     "fb_server_get_stats": (ctypes.c_int, [_p, ctypes.POINTER(FbServerStats)]),
     "fb_server_destroy": (ctypes.c_int, [_p]),
     "fb_monotonic_seconds": (_d, []),
@@ -558,6 +559,9 @@ class Server:
         return st.value
 
     def result(self, rid):
+        if rid not in self._shapes:   # read or released already (or never submitted here)
+            self.poll(rid)
+            raise FewbodyError(E_NOTFOUND, f"request {rid} has no result to read here")
         S, N = self._shapes.pop(rid)
         pos, vel = np.empty((N, 3)), np.empty((N, 3))
         t = np.empty(S)
@@ -571,6 +575,10 @@ class Server:
 
     def cancel(self, rid):
         _check(_lib.fb_server_cancel(self._h, int(rid)))
+
+    def release(self, rid):
+        _check(_lib.fb_server_release(self._h, int(rid)))
+        self._shapes.pop(rid, None)
 
     def stats(self) -> dict:
         st = FbServerStats()

@@ -178,13 +178,30 @@ def test_cancel_and_errors(fb):
     ens = gen.ragged_hill(8, seed=3, n_lo=3, n_hi=6)
     with fb.Server(steps_per_quantum=100) as srv:
         rid = srv.submit_gen(ens, 2 * math.pi * 200, H)
+        # not settled yet: it cannot be released
+        with pytest.raises(fb.FewbodyError) as ei:
+            srv.release(rid)
+        assert ei.value.code == fb.E_STATE
         srv.cancel(rid)
         assert srv.wait(rid, 60.0) == fb.REQ_CANCELLED
         with pytest.raises(fb.FewbodyError) as ei:
             srv.result(rid)
         assert ei.value.code == fb.E_STATE
+        # a settled request is forgotten on release
+        srv.release(rid)
+        for call in (srv.poll, srv.release):
+            with pytest.raises(fb.FewbodyError) as ei:
+                call(rid)
+            assert ei.value.code == fb.E_NOTFOUND
         with pytest.raises(fb.FewbodyError) as ei:
             srv.poll(10 ** 9)
+        assert ei.value.code == fb.E_NOTFOUND
+        # a done request may be released instead of read
+        rid = srv.submit_gen(ens, 2 * math.pi, H)
+        assert srv.wait(rid, 60.0) == fb.REQ_DONE
+        srv.release(rid)
+        with pytest.raises(fb.FewbodyError) as ei:
+            srv.result(rid)
         assert ei.value.code == fb.E_NOTFOUND
 
 
