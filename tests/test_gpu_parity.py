@@ -229,28 +229,32 @@ def test_persistent_equals_plain_bitwise(plans, cls):
         assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
 
 
-@pytest.mark.parametrize("n_sys", [65536, 3000])
-def test_adaptive_persistent_class_switches_are_bitwise_invisible(plans, n_sys):
-    """Adaptive steps with stop rules under compaction, automatic kernel
-    class: the run starts in the body-per-lane class and, once its waves no
-    longer give every SIMD two (at once for the smaller ensemble), moves to
-    unrolled body-per-lane tiles in the full-register class, and, once those
-    tiles no longer outnumber the kernel's waves (also at once for the
-    smaller ensemble), to 64-fold quanta.  The states, step counts and
-    statuses equal bitwise those of the plain schedule run system per lane
-    (a third mapping of the same arithmetic)."""
+@pytest.mark.parametrize("n_sys,mode", [(65536, "pairwise"), (3000, "pairwise"), (3000, "paper"),
+                                         (3000, "fixed")])
+def test_adaptive_persistent_class_switches_are_bitwise_invisible(plans, n_sys, mode):
+    """Stop rules under compaction, automatic kernel class, with the pairwise
+    step rule, Eq. 5's rule or fixed steps: the run starts in the body-per-
+    lane class and, once its waves no longer give every SIMD two (at once
+    for the smaller ensembles), moves to unrolled body-per-lane tiles in the
+    full-register class, and, once those tiles no longer outnumber the
+    kernel's waves (also at once for the smaller ensembles), to 64-fold
+    quanta.  The states, step counts and statuses equal bitwise those of the
+    plain schedule run system per lane (a third mapping of the same
+    arithmetic)."""
     fb = plans
     for n in range(2, 11):
         fb.set_plan(n, fb.MAP_SPL, 2, 0)
     fb.set_plan(0, fb.MAP_AUTO, 2, 8)
     ens, p = gen.workload("lifetimes_65536x4-8", n_sys=n_sys)
     t_end = 2 * math.pi * 3
-    base = dict(adaptive=True, eta=p["eta"], stop_rules=3, r_eject=p["r_eject"])
-    say("class switches vs plain", ens.n_sys)
+    rule = {"pairwise": 1, "paper": 2, "fixed": 0}[mode]
+    base = dict(adaptive=rule, eta=p["eta"] if rule == 1 else 1.7e-2, stop_rules=3, r_eject=p["r_eject"])
+    dt = 0.0 if rule else H2000
+    say("class switches vs plain", ens.n_sys, mode)
     out = []
     for o in (fb.Opts(**base), fb.Opts(schedule=fb.SCHED_PERSISTENT, steps_per_quantum=150, compact=True, **base)):
         E = fb.from_gen(ens)
-        E.integrate(t_end, 0.0, o)
+        E.integrate(t_end, dt, o)
         out.append(E.state())
         E.close()
     a, b = out
