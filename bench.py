@@ -236,13 +236,14 @@ def ragged_extras(fb, gen, torch, log):
 
 def lifetimes_extras(fb, gen, torch, log, orbits=100.0, quantum=2000):
     """Uneven lifetimes 65536 x (4..8): adaptive steps (eta 0.01) with the
-    close-encounter and ejection rules, on a bounded horizon of `orbits`
-    inner orbits (the workload's 1e4 orbits would take hours).  Plain: one
-    launch per bucket, retired lanes idle until their wave's last system
-    ends; persistent: quanta with in-kernel compaction of retired systems
-    (the fused-kernel class chosen automatically: system-per-lane while the
-    survivors fill the device, then body-per-lane; and, for comparison, the
-    body-per-lane class throughout)."""
+    close-encounter and ejection rules, on a horizon of `orbits` inner orbits
+    (100 by default, a bounded sample of the workload's 1e4, which takes about
+    23 s persistent and 83 s plain).  Plain: one launch per bucket, retired
+    lanes idle until their wave's last system ends; persistent: quanta with
+    in-kernel compaction of retired systems, the fused-kernel class chosen
+    automatically (body-per-lane, then the tail mode once the survivors'
+    waves no longer fill the device); and, for comparison, the body-per-lane
+    class throughout."""
     import numpy as np
     ens, p = gen.workload("lifetimes_65536x4-8")
     t_end = 2 * math.pi * orbits
