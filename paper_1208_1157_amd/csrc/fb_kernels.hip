@@ -954,9 +954,9 @@ __device__ __forceinline__ void bpl_eval_regs(BplLds &L, const int lane, const i
 }
 
 // Stop-rule flags (as bpl_stop_flags) and the system maximum of the step
-// rule's w (as sys_max) from one exchange: each lane publishes its position
-// and w, and forms its partners' astrocentric distances itself (the same
-// operations on the same values as the partners' own, so the same bits).
+// rule's w (as sys_max): one exchange of each lane's position and w gives
+// the star's position, the partners' positions and every w; a second, of
+// the astrocentric distances, the Hill test's partner radii.
 template <int N>
 __device__ __forceinline__ int bpl_stop_flags_regs(BplLds &L, const int lane, const int b,
                                                    const int s, const int (&pidx)[N - 1],
@@ -983,25 +983,30 @@ __device__ __forceinline__ int bpl_stop_flags_regs(BplLds &L, const int lane, co
 #pragma unroll
     for (int k = 0; k < N - 1; ++k)
         wsys = fmax(wsys, q1[k].y);
-    auto radius = [&](const double px, const double py, const double pz) {
-        const double dx = px - s0.x, dy = py - s0.y, dz = pz - s1.x;
-        return sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-    };
-    const double rb = radius(x[0], x[1], x[2]);
-    if (b >= 1) {
-        if ((P.stop_rules & 2) && rb > P.r_eject)
-            fl |= 4;
-        if (P.stop_rules & 1) {
+    const double dx = x[0] - s0.x, dy = x[1] - s0.y, dz = x[2] - s1.x;
+    const double rb = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    if (P.stop_rules & 1) {
+        // the partners' astrocentric distances: a second exchange is
+        // shorter than computing N - 2 more square roots per lane
+        double rp[N - 1];
+        L.mr[lane].y = rb;
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < N - 2; ++k)
+            rp[k] = L.mr[pidx[k]].y;
+        wave_sync();
+        if (b >= 1) {
 #pragma unroll
             for (int k = 0; k < N - 2; ++k) {
                 const double ex = x[0] - q0[k].x, ey = x[1] - q0[k].y, ez = x[2] - q1[k].x;
                 const double sep2 = fma(ez, ez, fma(ey, ey, ex * ex));
-                const double rj = radius(q0[k].x, q0[k].y, q1[k].x);
-                if (hill_close(sep2, mi, pm[k], inv24m0, rb, rj))
+                if (hill_close(sep2, mi, pm[k], inv24m0, rb, rp[k]))
                     fl |= 2;
             }
         }
     }
+    if (b >= 1 && (P.stop_rules & 2) && rb > P.r_eject)
+        fl |= 4;
     return sys_or_flags<N>(s, fl);
 }
 
