@@ -53,7 +53,7 @@ MEASURED_TRAFFIC = {"f56593fdeadf867b": 92376093.0, "a3428dc18039eedc": 92445596
                     "b0cf1370d8600140": 92417213.2, "d75718a170f1a208": 92400808.0,
                     "2e972ba6903455f7": 92417165.5, "b18c3be0358ab8a1": 92417237.0,
                     "1ed17940f99ee27b": 92404903.3, "0e3df7279f4c8f5d": 92412928.0,
-                    "51a920369b9cae68": 92407561.1}
+                    "51a920369b9cae68": 92407561.1, "ad207609a06017a7": 92422664.6}
 # Hardware counters of the same kernel on this workload from rocprofv3 runs
 # (profiles/), keyed the same way: FP64 flop per system-step from
 # SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; the fraction of SIMD cycles issuing
@@ -79,6 +79,8 @@ PROFILED_COUNTERS = {
                          "shader_clock_ghz": 2.114, "valu_insts_per_system_step": 388.0},
     "51a920369b9cae68": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9692,
                          "shader_clock_ghz": 2.066, "valu_insts_per_system_step": 388.0},
+    "ad207609a06017a7": {"fp64_flops_per_system_step": 672.0, "valu_busy": 0.9556,
+                         "shader_clock_ghz": 2.057, "valu_insts_per_system_step": 388.0},
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
