@@ -118,8 +118,9 @@ typedef struct {
     int32_t steps_per_quantum;  /* persistent schedule: steps per launch
                                    (<=0: whole run in one launch); with
                                    compact and the automatic fused class,
-                                   64x this once every surviving tile has a
-                                   wavefront of its own                         */
+                                   once every surviving tile has a
+                                   wavefront of its own, the rest of the run
+                                   goes in one launch                           */
     int32_t compact;            /* persistent schedule: rebuild tiles from the
                                    still-active systems after every quantum     */
 } fb_opts;

@@ -415,8 +415,6 @@ fb_status count_active(fb_ensemble *e, int &out)
 #ifndef FB_TAIL_WAVES_PER_SIMD
 #define FB_TAIL_WAVES_PER_SIMD 2
 #endif
-// Quantum growth in the tail (see run_persistent).
-constexpr long long kTailQuantumScale = 64;
 
 // Plain schedule: one launch per bucket (one per quantum if quanta are set).
 fb_status run_plain(fb_ensemble *e, const fb_opts &o, long long step_bound)
@@ -671,12 +669,13 @@ fb_status run_persistent(fb_ensemble *e, const fb_opts &o, long long step_bound)
                 recapture = true;
             }
         }
-        // Once every surviving tile has a wave of its own, the quantum
-        // boundary only makes each tile wait for the slowest one (tiles of
-        // 8 bodies take about 1.7x as long per step as tiles of 4), so the
-        // quanta grow kTailQuantumScale-fold and each tile runs on.
+        // Once every surviving tile has a wave of its own, compaction has
+        // nothing left to gain and a quantum boundary only makes each tile
+        // wait for the slowest one (8-body tiles take about 1.7x as long per
+        // step as 4-body ones, and the tiles' step counts differ), so the
+        // tiles run on to their ends in one launch.
         if (tail_mode && P.quantum == quantum && bpl_waves <= (long long)grid * W) {
-            P.quantum = (int)std::min<long long>((long long)quantum * kTailQuantumScale, INT_MAX / 2);
+            P.quantum = INT_MAX / 2;
             recapture = true;
         }
         if (recapture)

@@ -237,8 +237,8 @@ def test_adaptive_persistent_class_switches_are_bitwise_invisible(plans, n_sys, 
     lane class and, once its waves no longer give every SIMD two (at once
     for the smaller ensembles), moves to unrolled body-per-lane tiles in the
     full-register class, and, once those tiles no longer outnumber the
-    kernel's waves (also at once for the smaller ensembles), to 64-fold
-    quanta.  The states, step counts and statuses equal bitwise those of the
+    kernel's waves (also at once for the smaller ensembles), runs them to
+    their ends in one launch.  The states, step counts and statuses equal bitwise those of the
     plain schedule run system per lane (a third mapping of the same
     arithmetic)."""
     fb = plans
