@@ -422,6 +422,16 @@ fb_status fb_profile_read(double *kernel_ms, int64_t *launches);
  * nothing of the method.) */
 fb_status fb_fp64_fma_ceiling(double *tflops);
 
+/* The device's LDS streaming rates per CU, in GB/s, for whole-wavefront
+ * 16-byte reads (ds_read_b128) and writes (ds_write_b128): the best of two
+ * timed launches (8 workgroups of 256 lanes per CU, each streaming 16 KB of
+ * LDS slots, 64 consecutive per wavefront) per kind.  The body-per-lane
+ * kernels exchange each evaluation's state through LDS (Section 4.2's
+ * shared-memory staging), so these bound what an exchange costs.  Allocates
+ * and frees its own buffers on the current device and synchronises.  (A
+ * measurement utility; it computes nothing of the method.) */
+fb_status fb_lds_rates(double *read_gbs_per_cu, double *write_gbs_per_cu);
+
 /* The reciprocal square root every pair evaluation uses (Eq. 1's 1/|r|^3
  * and the jerk's 1/|r|^2 come from it; Section 4.4 discusses the hardware
  * rsqrt the paper relied on), applied elementwise to n DEVICE values x > 0:

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfewbody.so")
-SOURCES = ["fb_kernels.hip", "fb_runtime.cpp", "fb_server.cpp", "fb_solo.cpp"]
+SOURCES = ["fb_kernels.hip", "fb_runtime.cpp", "fb_server.cpp", "fb_solo.cpp", "fb_probes.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

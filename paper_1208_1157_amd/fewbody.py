@@ -117,6 +117,7 @@ _SIGS = {
     "fb_server_create": (ctypes.c_int, [ctypes.POINTER(FbServerOpts), _p, ctypes.POINTER(_p)]),
     "fb_server_request_bytes": (_sz, [ctypes.POINTER(FbServerOpts), _i32, _p]),
     "fb_fp64_fma_ceiling": (ctypes.c_int, [_p]),
+    "fb_lds_rates": (ctypes.c_int, [_p, _p]),
     "fb_server_submit": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p, _d, _d, ctypes.POINTER(_i64)]),
     "fb_server_poll": (ctypes.c_int, [_p, _i64, ctypes.POINTER(_i32)]),
     "fb_server_wait": (ctypes.c_int, [_p, _i64, _d, ctypes.POINTER(_i32)]),
@@ -199,6 +200,14 @@ def fp64_fma_ceiling() -> float:
     v = ctypes.c_double()
     _check(_lib.fb_fp64_fma_ceiling(ctypes.byref(v)))
     return v.value
+
+
+def lds_rates():
+    """LDS streaming rates of the current device per CU in GB/s, as
+    (16-byte wavefront reads, 16-byte wavefront writes) (fb_lds_rates)."""
+    r, w = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.fb_lds_rates(ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
 
 
 def profile_read():

@@ -140,6 +140,12 @@ def test_fma_ceiling_rejects_null(fbmod):
     assert fbmod.lib().fb_fp64_fma_ceiling(None) == fbmod.E_INVAL
 
 
+def test_lds_rates_rejects_null(fbmod):
+    x = ctypes.c_double()
+    assert fbmod.lib().fb_lds_rates(None, ctypes.byref(x)) == fbmod.E_INVAL
+    assert fbmod.lib().fb_lds_rates(ctypes.byref(x), None) == fbmod.E_INVAL
+
+
 def test_log_bytes(fbmod):
     """Log buffer sizes follow the documented layouts; invalid kinds, record
     counts and body counts give 0."""

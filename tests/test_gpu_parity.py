@@ -472,3 +472,10 @@ def test_fp64_fma_ceiling(fb):
     v = fb.fp64_fma_ceiling()
     say("fma ceiling", v)
     assert 5.0 < v < 100.0
+
+
+def test_lds_rates(fb):
+    """The LDS probe returns plausible per-CU rates (GB/s) for both kinds."""
+    r, w = fb.lds_rates()
+    say("LDS GB/s per CU: read", r, "write", w)
+    assert 50.0 < r < 4000.0 and 20.0 < w < 4000.0
